@@ -1,0 +1,181 @@
+/*
+ * bidiag.h -- C ABI of libbidiag: tiled band bidiagonalization on AMD MI355X.
+ *
+ * Operation (Faverge, Langou, Robert, Dongarra, "Bidiagonalization with
+ * Parallel Tiled Algorithms", Sections 3.4 and 3.5): for an m x n matrix A
+ * with m >= n and a tile size nb, compute orthogonal Q and P with
+ *
+ *     B = Q^T A P,     B(i,j) = 0 unless 0 <= j - i <= nb,   rows >= n zero,
+ *
+ * by alternating QR and LQ tile-panel eliminations along a reduction tree:
+ *   BiDiag   : QR(1); LQ(1); QR(2); ...; QR(q-1); LQ(q-1); QR(q)   (Section 3.4)
+ *   R-BiDiag : QR(p,q); LQ(1); QR(2); ...; LQ(q-1); QR(q)           (Section 3.5)
+ * where p = ceil(m/nb), q = ceil(n/nb) and each step uses the tile kernels of
+ * Table 1 (GEQRT/TSQRT/TTQRT and UNMQR/TSMQR/TTMQR, Algorithms 2 and 3; the LQ
+ * steps use the same kernels on transposed tiles, Algorithm 4).  Trees:
+ * FlatTS, FlatTT and Greedy (Section 3.3) and Auto (Section 5).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major FP64 in device memory, leading dimension
+ *     lda >= max(1, m).  m and n need not be multiples of nb: the last tile
+ *     row/column is handled as if zero-padded (padding is never read or
+ *     written in memory).
+ *   - All device buffers are owned by the caller.  The library never frees or
+ *     retains them past the call.  A plan owns a small device copy of its task
+ *     graph (allocated at the plan's first execution on a device, freed by
+ *     bb_plan_destroy).
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL means
+ *     the default stream) and is asynchronous: results are valid once the
+ *     stream has reached the enqueued work.
+ *   - Return codes: BB_OK (0); -i when argument i (1-based) is invalid, in the
+ *     LAPACK convention; a positive BB_E* code for runtime errors.  No C++
+ *     exception crosses the ABI.
+ *   - Reentrancy: calls with distinct plans and buffers may run concurrently;
+ *     one plan's executions must not overlap on the same workspace.
+ */
+#ifndef BIDIAG_H
+#define BIDIAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define BB_OK        0
+#define BB_ENOTSUP   1   /* valid but unsupported request (e.g. m < n, nb not in {32,64,128}) */
+#define BB_EHIP      2   /* a HIP runtime call failed */
+#define BB_ETIMEOUT  3   /* the device scheduler's watchdog fired (no progress) */
+#define BB_EDAG      4   /* the task graph failed validation on the host */
+#define BB_ENOMEM    5   /* host or device allocation for the plan failed */
+#define BB_EWORKSPACE 6  /* workspace or V/T buffer smaller than bb_plan_workspace reports */
+
+/* ---- enumerations ------------------------------------------------------ */
+/* Reduction trees: Section 3.3 (FlatTS, FlatTT, Greedy) and Section 5 (Auto). */
+enum { BB_FLATTS = 0, BB_FLATTT = 1, BB_GREEDY = 2, BB_AUTO = 3 };
+/* Algorithms: Section 3.4 (BiDiag), Section 3.5 (R-BiDiag).  BB_QRONLY runs
+ * only the tiled QR factorization QR(p,q) of Algorithm 1 (A is overwritten by
+ * R, rows >= n zero). */
+enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2 };
+/* Arithmetic: BB_F64 computes everything in FP64. */
+enum { BB_F64 = 0 };
+/* Execution of the task graph: one persistent launch whose workgroups take
+ * tasks in a precomputed priority order and wait on dependency counters
+ * (default), or one launch per topological level of the graph. */
+enum { BB_SCHED_PERSISTENT = 0, BB_SCHED_LEVELS = 1 };
+
+typedef struct {
+    int    workgroups;   /* workers assumed by Auto and used by the persistent
+                            launch; 0 = number of compute units */
+    double gamma;        /* Auto parallelism factor (Section 5); 0 = 2.0 */
+    int    auto_a;       /* > 0 forces Auto's FlatTS domain size; 0 = per step */
+    int    sched;        /* BB_SCHED_* */
+    double watchdog_s;   /* persistent scheduler: seconds without progress before
+                            BB_ETIMEOUT; 0 = 30 s */
+    int    flags;        /* BB_FLAG_* */
+} bb_opts;
+
+#define BB_FLAG_TIMING 1  /* record HIP events around the main kernel(s) */
+
+typedef struct bb_plan bb_plan;
+
+typedef struct {
+    int32_t p, q, nb;
+    int64_t ntasks;          /* kernel invocations in the graph */
+    int64_t nunits;          /* scheduled work units (updates split in column strips) */
+    int64_t nslots;          /* V/T records (one per panel task) */
+    int64_t nlevels;         /* topological levels */
+    int64_t count_by_kind[6];/* GEQRT, TSQRT, TTQRT, UNMQR, TSMQR, TTMQR (QR and LQ) */
+    double  critical_path;   /* longest path with Table 1 weights, units of nb^3/3 */
+    double  total_weight;    /* sum of Table 1 weights over all tasks */
+} bb_plan_stats;
+
+/*
+ * bb_plan_create -- build the task graph of one reduction (host only, no GPU
+ * call).  Arguments: out plan (1), m (2), n (3) with m >= n >= 1, nb (4) in
+ * {32, 64, 128}, tree (5) BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64,
+ * opts (8, may be NULL for defaults).  The plan is independent of the data and
+ * of lda; it can be executed any number of times.
+ */
+int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int variant,
+                   int prec, const bb_opts* opts);
+
+/* Release a plan and its device copy of the task graph. NULL is ignored. */
+void bb_plan_destroy(bb_plan* plan);
+
+/*
+ * Bytes of device memory the caller must provide to bb_execute:
+ *   vt_bytes : reflector records, one per panel task: V (nb x nb), V^T and
+ *              T^T (upper-triangular T of the compact WY form Q = I - V T V^T),
+ *              all FP64 column-major.  Kept after the call (Q and P are the
+ *              products of these records in task order).
+ *   ws_bytes : scheduler state (dependency counters, ticket, error flag).
+ */
+int bb_plan_workspace(const bb_plan* plan, size_t* vt_bytes, size_t* ws_bytes);
+
+int bb_plan_get_stats(const bb_plan* plan, bb_plan_stats* stats);
+
+/*
+ * Export the task graph in program order, for inspection and static checks.
+ * tasks: ntasks x 8 int32 {kind, trans, r1, c1, r2, c2, slot, step} with
+ * physical tile coordinates (see plan.hpp); pred_off: ntasks+1 offsets into
+ * pred_idx.  Pass NULL arrays to query *npred only.
+ */
+int bb_plan_export(const bb_plan* plan, int32_t* tasks, int32_t* pred_off, int32_t* pred_idx,
+                   int64_t* npred);
+
+/*
+ * bb_execute -- reduce A in place to its band form B (Sections 3.4/3.5).
+ * A (2): device, column-major, lda (3) >= m.  On completion A holds B with
+ * exact zeros outside the band.  vt (4) / ws (6): device buffers of at least
+ * the sizes from bb_plan_workspace (5, 7).  stream (8): hipStream_t or NULL.
+ * Returns after enqueueing; device-side scheduler failures (watchdog) are
+ * reported by bb_poll_error after the stream has completed.
+ */
+int bb_execute(bb_plan* plan, void* A, int64_t lda, void* vt, size_t vt_bytes, void* ws,
+               size_t ws_bytes, void* stream);
+
+/*
+ * bidiag_band -- one-shot form of bb_plan_create + bb_execute with a plan
+ * cached inside the library by (m, n, nb, tree, variant, prec, opts).
+ * Argument numbering: A (1), m (2), n (3), lda (4), nb (5), tree (6),
+ * variant (7), prec (8), vt (9), vt_bytes (10), ws (11), ws_bytes (12),
+ * opts (13), stream (14).
+ */
+int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, int variant,
+                int prec, void* vt, size_t vt_bytes, void* ws, size_t ws_bytes,
+                const bb_opts* opts, void* stream);
+
+/* Workspace sizes for bidiag_band with the same arguments. */
+int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
+             size_t* vt_bytes, size_t* ws_bytes);
+
+/*
+ * bb_poll_error -- synchronize `stream` and read the scheduler's error word
+ * from ws: *device_status = 0 if the last execution completed, else a BB_E*
+ * code.  Returns BB_OK or BB_EHIP.
+ */
+int bb_poll_error(const void* ws, void* stream, int* device_status);
+
+/*
+ * Milliseconds between the HIP events recorded around the main kernel(s) of
+ * the last bb_execute of this plan (requires BB_FLAG_TIMING; synchronizes on
+ * the end event).  For BB_SCHED_PERSISTENT this is the one persistent launch.
+ */
+int bb_plan_last_kernel_ms(bb_plan* plan, double* ms);
+
+/*
+ * Critical path (Section 4) of the task graph for a p x q tile matrix, with
+ * the Table 1 weights, host only.  Returns a negative value on bad input.
+ */
+double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int workgroups,
+                        double gamma);
+
+const char* bb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIDIAG_H */

@@ -1,0 +1,225 @@
+"""Python binding of libbidiag: tiled band bidiagonalization on MI355X (gfx950).
+
+Thin ctypes layer over the C ABI in ``include/bidiag.h``: it marshals
+arguments and uses PyTorch only for device memory and the current HIP stream.
+Every step of the reduction runs in the library's HIP kernels; if the library
+is missing this module raises instead of computing anything itself.
+
+Band form (Sections 3.4 and 3.5 of the paper): B = Q^T A P with B(i,j) = 0
+unless 0 <= j - i <= nb, reached by BiDiag or R-BiDiag with the FlatTS,
+FlatTT, Greedy or Auto reduction trees.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbidiag.so")
+
+TREES = {"flatts": 0, "flattt": 1, "greedy": 2, "auto": 3}
+VARIANTS = {"bidiag": 0, "rbidiag": 1, "qronly": 2}
+PRECS = {"f64": 0}
+SCHEDS = {"persistent": 0, "levels": 1}
+KINDS = ["GEQRT", "TSQRT", "TTQRT", "UNMQR", "TSMQR", "TTMQR"]
+FLAG_TIMING = 1
+
+
+class BidiagError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (code %d)" % (where, strerror(code), code))
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("auto_a", ctypes.c_int), ("sched", ctypes.c_int),
+                ("watchdog_s", ctypes.c_double), ("flags", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("ntasks", ctypes.c_int64), ("nunits", ctypes.c_int64),
+                ("nslots", ctypes.c_int64), ("nlevels", ctypes.c_int64),
+                ("count_by_kind", ctypes.c_int64 * 6), ("critical_path", ctypes.c_double),
+                ("total_weight", ctypes.c_double)]
+
+
+_lib = None
+
+# Every symbol include/bidiag.h declares.
+EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_get_stats",
+           "bb_plan_export", "bb_execute", "bidiag_band", "bb_query", "bb_poll_error",
+           "bb_plan_last_kernel_ms", "bb_critical_path", "bb_strerror"]
+
+
+def lib():
+    """Load libbidiag.so (built by ``python -m paper_1611_06892_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbidiag.so is not built (%s); run python -m "
+                          "paper_1611_06892_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    P = ctypes.c_void_p
+    L.bb_plan_create.argtypes = [ctypes.POINTER(P), i64, i64, i32, i32, i32, i32,
+                                 ctypes.POINTER(_Opts)]
+    L.bb_plan_create.restype = i32
+    L.bb_plan_destroy.argtypes = [P]
+    L.bb_plan_destroy.restype = None
+    L.bb_plan_workspace.argtypes = [P, ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    L.bb_plan_workspace.restype = i32
+    L.bb_plan_get_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    L.bb_plan_get_stats.restype = i32
+    L.bb_plan_export.argtypes = [P, vp, vp, vp, ctypes.POINTER(i64)]
+    L.bb_plan_export.restype = i32
+    L.bb_execute.argtypes = [P, vp, i64, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp]
+    L.bb_execute.restype = i32
+    L.bidiag_band.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, vp, ctypes.c_size_t, vp,
+                              ctypes.c_size_t, ctypes.POINTER(_Opts), vp]
+    L.bidiag_band.restype = i32
+    L.bb_query.argtypes = [i64, i64, i32, i32, i32, i32, ctypes.POINTER(_Opts),
+                           ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    L.bb_query.restype = i32
+    L.bb_poll_error.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
+    L.bb_poll_error.restype = i32
+    L.bb_plan_last_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    L.bb_plan_last_kernel_ms.restype = i32
+    L.bb_critical_path.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_double]
+    L.bb_critical_path.restype = ctypes.c_double
+    L.bb_strerror.argtypes = [i32]
+    L.bb_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().bb_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise BidiagError(rc, where)
+
+
+def make_opts(workgroups=0, gamma=0.0, auto_a=0, sched="persistent", watchdog_s=0.0,
+              timing=False) -> _Opts:
+    return _Opts(int(workgroups), float(gamma), int(auto_a), SCHEDS[sched], float(watchdog_s),
+                 FLAG_TIMING if timing else 0)
+
+
+def critical_path(p: int, q: int, tree="greedy", variant="bidiag", auto_a=0, workgroups=256,
+                  gamma=2.0) -> float:
+    """Critical path (Section 4) in units of nb^3/3 with Table 1 weights."""
+    return lib().bb_critical_path(p, q, TREES[tree], VARIANTS[variant], auto_a, workgroups, gamma)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Task graph and schedule of one (m, n, nb, tree, variant) reduction."""
+
+    def __init__(self, m, n, nb, tree="auto", variant="bidiag", prec="f64", **opts):
+        self.m, self.n, self.nb = int(m), int(n), int(nb)
+        self.tree, self.variant, self.prec = tree, variant, prec
+        self._opts = make_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(lib().bb_plan_create(ctypes.byref(h), self.m, self.n, self.nb, TREES[tree],
+                                    VARIANTS[variant], PRECS[prec], ctypes.byref(self._opts)),
+               "bb_plan_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bb_plan_destroy(h)
+            self._h = None
+
+    def workspace(self):
+        vt, ws = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().bb_plan_workspace(self._h, ctypes.byref(vt), ctypes.byref(ws)),
+               "bb_plan_workspace")
+        return vt.value, ws.value
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().bb_plan_get_stats(self._h, ctypes.byref(s)), "bb_plan_get_stats")
+        return {"p": s.p, "q": s.q, "nb": s.nb, "ntasks": s.ntasks, "nunits": s.nunits,
+                "nslots": s.nslots, "nlevels": s.nlevels,
+                "count_by_kind": dict(zip(KINDS, list(s.count_by_kind))),
+                "critical_path": s.critical_path, "total_weight": s.total_weight}
+
+    def export(self):
+        """(tasks[ntasks, 8], pred_off[ntasks+1], pred_idx[npred]) as int32 arrays."""
+        npred = ctypes.c_int64()
+        _check(lib().bb_plan_export(self._h, None, None, None, ctypes.byref(npred)),
+               "bb_plan_export")
+        nt = self.stats()["ntasks"]
+        tasks = np.zeros((nt, 8), dtype=np.int32)
+        off = np.zeros(nt + 1, dtype=np.int32)
+        idx = np.zeros(max(1, npred.value), dtype=np.int32)
+        _check(lib().bb_plan_export(self._h, tasks.ctypes.data, off.ctypes.data, idx.ctypes.data,
+                                    ctypes.byref(npred)), "bb_plan_export")
+        return tasks, off, idx[:npred.value]
+
+    def alloc(self, device=None):
+        """Allocate (vt, ws) byte buffers of the sizes this plan needs."""
+        import torch
+        vt_b, ws_b = self.workspace()
+        dev = device if device is not None else torch.device("cuda")
+        vt = torch.empty(max(vt_b, 8), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(ws_b, 8), dtype=torch.uint8, device=dev)
+        return vt, ws
+
+    def execute(self, Acm, lda, vt, ws, stream=None):
+        """Reduce the column-major matrix at Acm (a CUDA tensor whose storage is
+        m x n column-major with leading dimension lda) in place."""
+        _check(lib().bb_execute(self._h, ctypes.c_void_p(Acm.data_ptr()), int(lda),
+                                ctypes.c_void_p(vt.data_ptr()), vt.numel() * vt.element_size(),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                _stream_handle(stream)), "bb_execute")
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(lib().bb_plan_last_kernel_ms(self._h, ctypes.byref(ms)), "bb_plan_last_kernel_ms")
+        return ms.value
+
+
+def poll_error(ws, stream=None) -> int:
+    st = ctypes.c_int()
+    _check(lib().bb_poll_error(ctypes.c_void_p(ws.data_ptr()), _stream_handle(stream),
+                               ctypes.byref(st)), "bb_poll_error")
+    return st.value
+
+
+def to_colmajor(A):
+    """Column-major device copy of a 2-D tensor: returns the (n, m) row-major
+    storage tensor S with S[j, i] = A[i, j] (so S.t() is A)."""
+    import torch
+    return A.to(device="cuda", dtype=torch.float64).t().contiguous()
+
+
+def band(A, nb, tree="auto", variant="bidiag", plan=None, check=True, **opts):
+    """Band-bidiagonalize A (m x n, m >= n).  Returns (B, vt, plan) where B is
+    an m x n CUDA tensor view holding the band form and vt the reflector
+    records.  A is not modified."""
+    m, n = A.shape
+    S = to_colmajor(A)
+    if plan is None:
+        plan = Plan(m, n, nb, tree, variant, **opts)
+    vt, ws = plan.alloc(S.device)
+    plan.execute(S, m, vt, ws)
+    if check:
+        st = poll_error(ws)
+        if st != 0:
+            raise BidiagError(st, "device scheduler")
+    return S.t(), vt, plan

@@ -1,0 +1,530 @@
+// C ABI of libbidiag (declarations and contracts in include/bidiag.h).
+//
+// A plan holds the task graph of one (m, n, nb, tree, variant) reduction, the
+// execution order of its work units and a lazily uploaded device copy of all
+// of it.  Execution enqueues either one persistent scheduler launch or one
+// launch per topological level on the caller's stream.
+#include "../../include/bidiag.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <queue>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct bb_plan {
+    int64_t m = 0, n = 0;
+    int nb = 0, tree = 0, variant = 0, prec = 0;
+    bb_opts opts{};
+    bb::Graph g;
+    int ns = 0;                              // update strip width
+    std::vector<int32_t> nparts, ndeps, succ_off, succ_idx;
+    std::vector<int32_t> units_ticket;       // (task, part) pairs, priority order
+    std::vector<int32_t> units_level;        // (task, part) pairs sorted by level
+    std::vector<int32_t> level_off;          // units_level offsets per level
+    double cp = 0.0, total = 0.0;
+    // device copy of the graph and schedule
+    int device = -1;
+    void* dblob = nullptr;
+    size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_ut = 0, off_ul = 0;
+    int cu_count = 0;
+    double wallclock_khz = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+namespace {
+
+const double kUnit[6] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0};   // Table 1
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Host validation of a schedule: predecessors precede each task in program
+// order and in ticket order, and the dependency counts match the graph.
+bool validate(const bb_plan& P) {
+    const size_t nt = P.g.tasks.size();
+    const size_t nu = P.units_ticket.size() / 2;
+    std::vector<int64_t> first(nt, -1), last(nt, -1);
+    for (size_t u = 0; u < nu; ++u) {
+        int t = P.units_ticket[2 * u];
+        if (t < 0 || (size_t)t >= nt) return false;
+        if (first[t] < 0) first[t] = (int64_t)u;
+        last[t] = (int64_t)u;
+    }
+    for (size_t t = 0; t < nt; ++t) {
+        if (first[t] < 0) return false;
+        int32_t nd = 0;
+        for (int32_t pr : P.g.pred[t]) {
+            if (pr < 0 || (size_t)pr >= t) return false;
+            if (last[pr] >= first[t]) return false;
+            nd += P.nparts[pr];
+        }
+        if (nd != P.ndeps[t]) return false;
+    }
+    return true;
+}
+
+int build_schedule(bb_plan& P) {
+    const bb::Graph& g = P.g;
+    const int nt = (int)g.tasks.size();
+    P.ns = bbk::strip_width(P.nb);
+    P.nparts.assign(nt, 1);
+    for (int t = 0; t < nt; ++t)
+        if (!bb::is_panel(g.tasks[t].kind)) P.nparts[t] = (P.nb + P.ns - 1) / P.ns;
+    P.ndeps.assign(nt, 0);
+    std::vector<int32_t> cnt(nt + 1, 0);
+    for (int t = 0; t < nt; ++t) {
+        for (int32_t pr : g.pred[t]) {
+            P.ndeps[t] += P.nparts[pr];
+            cnt[pr + 1]++;
+        }
+    }
+    P.succ_off.assign(nt + 1, 0);
+    for (int t = 0; t < nt; ++t) P.succ_off[t + 1] = P.succ_off[t] + cnt[t + 1];
+    P.succ_idx.assign(P.succ_off[nt], 0);
+    std::vector<int32_t> fill(P.succ_off.begin(), P.succ_off.end() - 1);
+    for (int t = 0; t < nt; ++t)
+        for (int32_t pr : g.pred[t]) P.succ_idx[fill[pr]++] = t;
+
+    // Priorities: bottom level (longest weighted path from the task to the end).
+    std::vector<double> blevel(nt, 0.0);
+    for (int t = nt - 1; t >= 0; --t) {
+        double b = 0.0;
+        for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) b = std::max(b, blevel[P.succ_idx[s]]);
+        blevel[t] = b + kUnit[g.tasks[t].kind];
+    }
+    P.cp = 0.0;
+    P.total = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        P.cp = std::max(P.cp, blevel[t]);
+        P.total += kUnit[g.tasks[t].kind];
+    }
+
+    // Ticket order: list scheduling of the units on W workers, highest bottom
+    // level first; the order in which units start is the ticket order.
+    const int W = std::max(1, P.opts.workgroups);
+    typedef std::tuple<double, int, int> RK;   // (-priority, task, part)
+    std::priority_queue<RK, std::vector<RK>, std::greater<RK>> ready;
+    typedef std::tuple<double, int> EV;        // (finish time, task)
+    std::priority_queue<EV, std::vector<EV>, std::greater<EV>> running;
+    std::vector<int32_t> indeg(nt), left(nt);
+    for (int t = 0; t < nt; ++t) {
+        indeg[t] = (int32_t)g.pred[t].size();
+        left[t] = P.nparts[t];
+        if (indeg[t] == 0)
+            for (int q = 0; q < P.nparts[t]; ++q) ready.emplace(-blevel[t], t, q);
+    }
+    P.units_ticket.clear();
+    double now = 0.0;
+    int busy = 0;
+    while (!ready.empty() || !running.empty()) {
+        while (busy < W && !ready.empty()) {
+            RK r = ready.top();
+            ready.pop();
+            int t = std::get<1>(r);
+            P.units_ticket.push_back(t);
+            P.units_ticket.push_back(std::get<2>(r));
+            running.emplace(now + kUnit[g.tasks[t].kind] / P.nparts[t], t);
+            busy++;
+        }
+        if (running.empty()) break;
+        EV e = running.top();
+        running.pop();
+        now = std::get<0>(e);
+        busy--;
+        int t = std::get<1>(e);
+        if (--left[t] == 0) {
+            for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) {
+                int v = P.succ_idx[s];
+                if (--indeg[v] == 0)
+                    for (int q = 0; q < P.nparts[v]; ++q) ready.emplace(-blevel[v], v, q);
+            }
+        }
+    }
+
+    // Levels: longest path, in tasks, from a source.
+    std::vector<int32_t> level(nt, 0);
+    int nlev = 0;
+    for (int t = 0; t < nt; ++t) {
+        int l = 0;
+        for (int32_t pr : g.pred[t]) l = std::max(l, level[pr] + 1);
+        level[t] = l;
+        nlev = std::max(nlev, l + 1);
+    }
+    const size_t nu = P.units_ticket.size() / 2;
+    P.level_off.assign(nlev + 1, 0);
+    for (size_t u = 0; u < nu; ++u) P.level_off[level[P.units_ticket[2 * u]] + 1]++;
+    for (int l = 0; l < nlev; ++l) P.level_off[l + 1] += P.level_off[l];
+    P.units_level.assign(2 * nu, 0);
+    std::vector<int32_t> lf(P.level_off.begin(), P.level_off.end() - 1);
+    for (size_t u = 0; u < nu; ++u) {
+        int t = P.units_ticket[2 * u];
+        int pos = lf[level[t]]++;
+        P.units_level[2 * pos] = t;
+        P.units_level[2 * pos + 1] = P.units_ticket[2 * u + 1];
+    }
+    return validate(P) ? BB_OK : BB_EDAG;
+}
+
+size_t ws_bytes_of(const bb_plan& P) {
+    return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256) +
+           round_up(sizeof(int32_t) * P.g.tasks.size(), 256);
+}
+
+size_t vt_bytes_of(const bb_plan& P) {
+    return (size_t)P.g.nslots * 3 * (size_t)P.nb * P.nb * sizeof(double);
+}
+
+// Upload the graph and schedule to the current device (once per plan).
+int ensure_device(bb_plan& P) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
+    if (P.dblob && P.device == dev) return BB_OK;
+    if (P.dblob) {
+        (void)hipFree(P.dblob);
+        P.dblob = nullptr;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BB_EHIP;
+    P.cu_count = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    P.wallclock_khz = (double)khz;
+
+    const size_t nt = P.g.tasks.size();
+    std::vector<bbk::DevTask> dt(nt);
+    for (size_t t = 0; t < nt; ++t) {
+        const bb::Task& s = P.g.tasks[t];
+        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, P.nparts[t]};
+    }
+    size_t off = 0;
+    P.off_tasks = off; off = round_up(off + nt * sizeof(bbk::DevTask), 256);
+    P.off_ndeps = off; off = round_up(off + nt * 4, 256);
+    P.off_succ_off = off; off = round_up(off + P.succ_off.size() * 4, 256);
+    P.off_succ_idx = off; off = round_up(off + std::max<size_t>(1, P.succ_idx.size()) * 4, 256);
+    P.off_ut = off; off = round_up(off + P.units_ticket.size() * 4, 256);
+    P.off_ul = off; off = round_up(off + P.units_level.size() * 4, 256);
+    std::vector<char> host(off, 0);
+    std::memcpy(host.data() + P.off_tasks, dt.data(), nt * sizeof(bbk::DevTask));
+    std::memcpy(host.data() + P.off_ndeps, P.ndeps.data(), nt * 4);
+    std::memcpy(host.data() + P.off_succ_off, P.succ_off.data(), P.succ_off.size() * 4);
+    if (!P.succ_idx.empty()) std::memcpy(host.data() + P.off_succ_idx, P.succ_idx.data(), P.succ_idx.size() * 4);
+    std::memcpy(host.data() + P.off_ut, P.units_ticket.data(), P.units_ticket.size() * 4);
+    std::memcpy(host.data() + P.off_ul, P.units_level.data(), P.units_level.size() * 4);
+    void* d = nullptr;
+    if (hipMalloc(&d, off) != hipSuccess) return BB_ENOMEM;
+    if (hipMemcpy(d, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return BB_EHIP;
+    }
+    P.dblob = d;
+    P.device = dev;
+    return BB_OK;
+}
+
+bb_opts resolved_opts(const bb_opts* o) {
+    bb_opts r{};
+    if (o) r = *o;
+    if (r.workgroups <= 0) {
+        r.workgroups = 0;   // resolved to the CU count at first execution
+    }
+    if (!(r.gamma > 0.0)) r.gamma = 2.0;
+    if (!(r.watchdog_s > 0.0)) r.watchdog_s = 30.0;
+    return r;
+}
+
+int default_workgroups() {
+    // Number of compute units of the current device if one is visible, else
+    // the MI355X count.  Only used for planning; no device work is enqueued.
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        return cus;
+    return 256;
+}
+
+std::mutex g_cache_mu;
+std::map<std::vector<double>, bb_plan*> g_cache;
+
+std::vector<double> cache_key(int64_t m, int64_t n, int nb, int tree, int variant, int prec,
+                              const bb_opts& o) {
+    return {(double)m, (double)n, (double)nb, (double)tree, (double)variant, (double)prec,
+            (double)o.workgroups, o.gamma, (double)o.auto_a, (double)o.sched, o.watchdog_s,
+            (double)o.flags};
+}
+
+}  // namespace
+
+extern "C" {
+
+int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int variant, int prec,
+                   const bb_opts* opts) {
+    if (!plan) return -1;
+    *plan = nullptr;
+    if (m < 1) return -2;
+    if (n < 1) return -3;
+    if (nb < 1) return -4;
+    if (tree < BB_FLATTS || tree > BB_AUTO) return -5;
+    if (variant < BB_BIDIAG || variant > BB_QRONLY) return -6;
+    if (prec != BB_F64) return -7;
+    if (m < n) return BB_ENOTSUP;
+    if (!bbk::nb_supported(nb)) return BB_ENOTSUP;
+    bb_opts o = resolved_opts(opts);
+    if (o.sched != BB_SCHED_PERSISTENT && o.sched != BB_SCHED_LEVELS) return -8;
+    if (o.workgroups <= 0) o.workgroups = default_workgroups();
+    int64_t p = (m + nb - 1) / nb, q = (n + nb - 1) / nb;
+    if (p > (1 << 20) || q > (1 << 16)) return BB_ENOTSUP;
+    bb_plan* P = new (std::nothrow) bb_plan();
+    if (!P) return BB_ENOMEM;
+    P->m = m; P->n = n; P->nb = nb; P->tree = tree; P->variant = variant; P->prec = prec;
+    P->opts = o;
+    bb::PlanOptions po;
+    po.tree = tree;
+    po.variant = variant;
+    po.workgroups = o.workgroups;
+    po.gamma = o.gamma;
+    po.auto_a = o.auto_a;
+    try {
+        std::string err = bb::build_graph((int)p, (int)q, po, P->g);
+        if (!err.empty()) {
+            delete P;
+            return BB_EDAG;
+        }
+        int rc = build_schedule(*P);
+        if (rc != BB_OK) {
+            delete P;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete P;
+        return BB_ENOMEM;
+    } catch (...) {
+        delete P;
+        return BB_EDAG;
+    }
+    *plan = P;
+    return BB_OK;
+}
+
+void bb_plan_destroy(bb_plan* P) {
+    if (!P) return;
+    if (P->dblob) (void)hipFree(P->dblob);
+    if (P->ev0) (void)hipEventDestroy(P->ev0);
+    if (P->ev1) (void)hipEventDestroy(P->ev1);
+    delete P;
+}
+
+int bb_plan_workspace(const bb_plan* P, size_t* vt_bytes, size_t* ws_bytes) {
+    if (!P) return -1;
+    if (vt_bytes) *vt_bytes = vt_bytes_of(*P);
+    if (ws_bytes) *ws_bytes = ws_bytes_of(*P);
+    return BB_OK;
+}
+
+int bb_plan_get_stats(const bb_plan* P, bb_plan_stats* s) {
+    if (!P) return -1;
+    if (!s) return -2;
+    std::memset(s, 0, sizeof(*s));
+    s->p = P->g.p;
+    s->q = P->g.q;
+    s->nb = P->nb;
+    s->ntasks = (int64_t)P->g.tasks.size();
+    s->nunits = (int64_t)P->units_ticket.size() / 2;
+    s->nslots = P->g.nslots;
+    s->nlevels = (int64_t)P->level_off.size() - 1;
+    for (const bb::Task& t : P->g.tasks) s->count_by_kind[t.kind]++;
+    s->critical_path = P->cp;
+    s->total_weight = P->total;
+    return BB_OK;
+}
+
+int bb_plan_export(const bb_plan* P, int32_t* tasks, int32_t* pred_off, int32_t* pred_idx,
+                   int64_t* npred) {
+    if (!P) return -1;
+    int64_t np = 0;
+    for (const auto& v : P->g.pred) np += (int64_t)v.size();
+    if (npred) *npred = np;
+    if (tasks) {
+        for (size_t t = 0; t < P->g.tasks.size(); ++t) {
+            const bb::Task& s = P->g.tasks[t];
+            int32_t* o = tasks + 8 * t;
+            o[0] = s.kind; o[1] = s.trans; o[2] = s.r1; o[3] = s.c1;
+            o[4] = s.r2; o[5] = s.c2; o[6] = s.slot; o[7] = s.step;
+        }
+    }
+    if (pred_off && pred_idx) {
+        int64_t k = 0;
+        for (size_t t = 0; t < P->g.tasks.size(); ++t) {
+            pred_off[t] = (int32_t)k;
+            for (int32_t pr : P->g.pred[t]) pred_idx[k++] = pr;
+        }
+        pred_off[P->g.tasks.size()] = (int32_t)k;
+    }
+    return BB_OK;
+}
+
+int bb_execute(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void* ws,
+               size_t ws_bytes, void* stream) {
+    if (!P) return -1;
+    if (!A) return -2;
+    if (lda < std::max<int64_t>(1, P->m)) return -3;
+    if (!vt) return -4;
+    if (vt_bytes < vt_bytes_of(*P)) return BB_EWORKSPACE;
+    if (!ws) return -6;
+    if (ws_bytes < ws_bytes_of(*P)) return BB_EWORKSPACE;
+    int rc = ensure_device(*P);
+    if (rc != BB_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+
+    bbk::KArgs a{};
+    a.A = (double*)A;
+    a.lda = lda;
+    a.m = P->m;
+    a.n = P->n;
+    a.vt = (double*)vt;
+    a.slot_stride = 3 * (int64_t)P->nb * P->nb;
+    char* blob = (char*)P->dblob;
+    a.tasks = (const bbk::DevTask*)(blob + P->off_tasks);
+    a.nunits = (int32_t)(P->units_ticket.size() / 2);
+    a.succ_off = (const int32_t*)(blob + P->off_succ_off);
+    a.succ_idx = (const int32_t*)(blob + P->off_succ_idx);
+    a.ctrl = (int32_t*)ws;
+    a.deps = (int32_t*)((char*)ws + round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256));
+    a.watchdog_ticks = (int64_t)(P->opts.watchdog_s * P->wallclock_khz * 1000.0);
+
+    const bool timed = (P->opts.flags & BB_FLAG_TIMING) != 0;
+    if (timed && !P->ev0) {
+        if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
+    }
+    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), s) !=
+        hipSuccess)
+        return BB_EHIP;
+    if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
+    if (P->opts.sched == BB_SCHED_PERSISTENT) {
+        a.units = (const int2*)(blob + P->off_ut);
+        int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
+        if (wg < 1) wg = 1;
+        if (bbk::launch_persistent(P->nb, a, wg, s) != hipSuccess) return BB_EHIP;
+    } else {
+        a.units = (const int2*)(blob + P->off_ul);
+        for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
+            int32_t b = P->level_off[l], e = P->level_off[l + 1];
+            if (bbk::launch_level(P->nb, a, b, e - b, s) != hipSuccess) return BB_EHIP;
+        }
+    }
+    if (timed && hipEventRecord(P->ev1, s) != hipSuccess) return BB_EHIP;
+    P->timed = timed;
+    return BB_OK;
+}
+
+int bb_plan_last_kernel_ms(bb_plan* P, double* ms) {
+    if (!P) return -1;
+    if (!ms) return -2;
+    if (!P->timed || !P->ev0) return BB_ENOTSUP;
+    if (hipEventSynchronize(P->ev1) != hipSuccess) return BB_EHIP;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, P->ev0, P->ev1) != hipSuccess) return BB_EHIP;
+    *ms = (double)f;
+    return BB_OK;
+}
+
+int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
+             size_t* vt_bytes, size_t* ws_bytes) {
+    bb_plan* P = nullptr;
+    int rc = bb_plan_create(&P, m, n, nb, tree, variant, prec, opts);
+    if (rc != BB_OK) return rc;
+    bb_plan_workspace(P, vt_bytes, ws_bytes);
+    bb_plan_destroy(P);
+    return BB_OK;
+}
+
+int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, int variant, int prec,
+                void* vt, size_t vt_bytes, void* ws, size_t ws_bytes, const bb_opts* opts,
+                void* stream) {
+    if (!A) return -1;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (!vt) return -9;
+    if (!ws) return -11;
+    bb_opts o = resolved_opts(opts);
+    std::vector<double> key = cache_key(m, n, nb, tree, variant, prec, o);
+    bb_plan* P = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            P = it->second;
+        } else {
+            int rc = bb_plan_create(&P, m, n, nb, tree, variant, prec, &o);
+            if (rc != BB_OK) {
+                // map plan-creation argument numbers onto this entry point's
+                if (rc < 0) {
+                    static const int remap[9] = {0, 0, -2, -3, -5, -6, -7, -8, -13};
+                    return rc >= -8 ? remap[-rc] : rc;
+                }
+                return rc;
+            }
+            g_cache[key] = P;
+        }
+    }
+    int rc = bb_execute(P, A, lda, vt, vt_bytes, ws, ws_bytes, stream);
+    if (rc == -3) return -4;
+    if (rc == -4) return -9;
+    if (rc == -6) return -11;
+    return rc;
+}
+
+int bb_poll_error(const void* ws, void* stream, int* device_status) {
+    if (!ws) return -1;
+    if (!device_status) return -3;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return BB_EHIP;
+    int32_t e = 0;
+    if (hipMemcpy(&e, (const char*)ws + sizeof(int32_t) * bbk::CTRL_ERROR, sizeof(int32_t),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return BB_EHIP;
+    *device_status = e;
+    return BB_OK;
+}
+
+double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int workgroups,
+                        double gamma) {
+    if (q < 1 || p < q) return -1.0;
+    bb::PlanOptions po;
+    po.tree = tree;
+    po.variant = variant;
+    po.auto_a = auto_a;
+    po.workgroups = workgroups > 0 ? workgroups : 256;
+    po.gamma = gamma > 0.0 ? gamma : 2.0;
+    bb::Graph g;
+    try {
+        if (!bb::build_graph(p, q, po, g).empty()) return -1.0;
+    } catch (...) {
+        return -1.0;
+    }
+    return bb::critical_path(g, bb::kTable1Weights);
+}
+
+const char* bb_strerror(int code) {
+    if (code < 0) return "invalid argument";
+    switch (code) {
+    case BB_OK: return "success";
+    case BB_ENOTSUP: return "unsupported request";
+    case BB_EHIP: return "HIP runtime error";
+    case BB_ETIMEOUT: return "device scheduler watchdog expired";
+    case BB_EDAG: return "task graph failed validation";
+    case BB_ENOMEM: return "out of memory";
+    case BB_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

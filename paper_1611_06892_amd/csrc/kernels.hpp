@@ -1,0 +1,41 @@
+// Interface between the host driver (api.cpp) and the gfx950 kernels
+// (kernels.hip).  Plain structs passed by value to the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bbk {
+
+// One task of the graph as the device reads it (physical tile coordinates).
+struct DevTask {
+    int32_t kind, trans, r1, c1, r2, c2, slot, nparts;
+};
+
+// Scheduler control words at the start of the workspace.
+enum : int { CTRL_TICKET = 0, CTRL_ERROR = 1, CTRL_DONE = 2, CTRL_WORDS = 64 };
+
+struct KArgs {
+    double* A;
+    int64_t lda, m, n;
+    double* vt;              // V/T records
+    int64_t slot_stride;     // doubles per record (3 nb^2)
+    const DevTask* tasks;
+    const int2* units;       // (task, part) in execution order
+    int32_t nunits;
+    const int32_t* succ_off; // CSR successors
+    const int32_t* succ_idx;
+    int32_t* deps;           // live dependency counters (persistent mode)
+    int32_t* ctrl;           // CTRL_* words
+    int64_t watchdog_ticks;  // wall-clock ticks without progress before giving up
+};
+
+// Update strip width (columns of the logical C tile per work unit).
+inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
+hipError_t launch_level(int nb, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
+hipError_t launch_persistent(int nb, const KArgs& a, int32_t workgroups, hipStream_t s);
+bool nb_supported(int nb);
+
+}  // namespace bbk

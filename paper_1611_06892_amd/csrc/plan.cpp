@@ -1,0 +1,232 @@
+// Task-graph planner: reduction trees, step sequences, tile dependencies and
+// critical paths.  See plan.hpp for the model.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace bb {
+
+const double kTable1Weights[6] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0};
+
+int auto_domain(int u, int v, int workgroups, double gamma) {
+    // Section 5: pick a per step so that ceil(u/a) * v parallel tasks are at
+    // least gamma * nb_cores; the largest such a keeps the most TS kernels.
+    double need = gamma * (double)workgroups;
+    int vv = v > 1 ? v : 1;
+    for (int a = u; a >= 1; --a) {
+        long long dom = (u + a - 1) / a;
+        if ((double)dom * (double)vv >= need) return a;
+    }
+    return 1;
+}
+
+std::vector<Elim> step_tree(int tree, int u, int a) {
+    std::vector<Elim> el;
+    if (u <= 1) return el;
+    switch (tree) {
+    case FLATTS:   // Section 3.3: pivot is the diagonal tile, eliminate in order, TS
+        for (int i = 1; i < u; ++i) el.push_back({i, 0, 0});
+        break;
+    case FLATTT:   // same eliminations with TT kernels
+        for (int i = 1; i < u; ++i) el.push_back({i, 0, 1});
+        break;
+    case GREEDY:   // one BiDiag step: binomial tree (Section 3.6), TT kernels
+        for (int s = 1; s < u; s *= 2)
+            for (int i = s; i < u; i += 2 * s) el.push_back({i, i - s, 1});
+        break;
+    case AUTO: {   // Section 5: FlatTS domains of size a joined by a Greedy TT tree
+        if (a < 1) a = 1;
+        int ndom = (u + a - 1) / a;
+        for (int d = 0; d < ndom; ++d) {
+            int head = d * a;
+            int end = std::min(head + a, u);
+            for (int i = head + 1; i < end; ++i) el.push_back({i, head, 0});
+        }
+        for (int s = 1; s < ndom; s *= 2)
+            for (int h = s; h < ndom; h += 2 * s) el.push_back({h * a, (h - s) * a, 1});
+        break;
+    }
+    default:
+        break;
+    }
+    return el;
+}
+
+namespace {
+
+struct Builder {
+    Graph& g;
+    int p, q;
+    std::vector<int32_t> last_writer;   // per physical tile
+    std::vector<int32_t> slot_owner;    // slot -> panel task
+
+    Builder(Graph& gg, int pp, int qq) : g(gg), p(pp), q(qq), last_writer((size_t)pp * qq, -1) {}
+
+    int32_t add(Task t) {
+        int32_t id = (int32_t)g.tasks.size();
+        std::vector<int32_t> pr;
+        auto touch = [&](int r, int c) {
+            if (r < 0) return;
+            int32_t& w = last_writer[(size_t)r * q + c];
+            if (w >= 0) pr.push_back(w);
+            w = id;
+        };
+        touch(t.r1, t.c1);
+        touch(t.r2, t.c2);
+        if (!is_panel(t.kind)) pr.push_back(slot_owner[t.slot]);
+        std::sort(pr.begin(), pr.end());
+        pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+        g.tasks.push_back(t);
+        g.pred.push_back(std::move(pr));
+        return id;
+    }
+
+    int32_t new_slot(int32_t owner_task) {
+        slot_owner.push_back(owner_task);
+        return g.nslots++;
+    }
+
+    // One QR step in the logical frame (trans = 1 for LQ): panel tiles
+    // (rows[li], kcol), trailing tiles (rows[li], cols[*]).
+    struct StepState {
+        int trans, kcol, step;
+        std::vector<int> rows, cols;
+        std::vector<char> tri;
+    };
+
+    void phys(int trans, int lr, int lc, int32_t& r, int32_t& c) const {
+        if (trans) { r = lc; c = lr; } else { r = lr; c = lc; }
+    }
+
+    void ensure_tri(StepState& s, int li) {
+        if (s.tri[li]) return;
+        Task t{GEQRT, s.trans, 0, 0, -1, -1, 0, s.step};
+        phys(s.trans, s.rows[li], s.kcol, t.r1, t.c1);
+        int32_t id = (int32_t)g.tasks.size();
+        t.slot = new_slot(id);
+        add(t);
+        for (int c : s.cols) {
+            Task u{UNMQR, s.trans, -1, -1, 0, 0, t.slot, s.step};
+            phys(s.trans, s.rows[li], c, u.r2, u.c2);
+            add(u);
+        }
+        s.tri[li] = 1;
+    }
+
+    void eliminate(StepState& s, const Elim& e) {
+        ensure_tri(s, e.piv);
+        if (e.tt) ensure_tri(s, e.i);
+        Task t{e.tt ? TTQRT : TSQRT, s.trans, 0, 0, 0, 0, 0, s.step};
+        phys(s.trans, s.rows[e.piv], s.kcol, t.r1, t.c1);
+        phys(s.trans, s.rows[e.i], s.kcol, t.r2, t.c2);
+        int32_t id = (int32_t)g.tasks.size();
+        t.slot = new_slot(id);
+        add(t);
+        for (int c : s.cols) {
+            Task u{e.tt ? TTMQR : TSMQR, s.trans, 0, 0, 0, 0, t.slot, s.step};
+            phys(s.trans, s.rows[e.piv], c, u.r1, u.c1);
+            phys(s.trans, s.rows[e.i], c, u.r2, u.c2);
+            add(u);
+        }
+    }
+
+    StepState make_step(int trans, int kcol, int r0, int r1, int c0, int c1) {
+        StepState s;
+        s.trans = trans;
+        s.kcol = kcol;
+        s.step = g.nsteps++;
+        for (int r = r0; r < r1; ++r) s.rows.push_back(r);
+        for (int c = c0; c < c1; ++c) s.cols.push_back(c);
+        s.tri.assign(s.rows.size(), 0);
+        return s;
+    }
+
+    void run_step(int trans, int kcol, int r0, int r1, int c0, int c1) {
+        StepState s = make_step(trans, kcol, r0, r1, c0, c1);
+        int u = (int)s.rows.size(), v = (int)s.cols.size();
+        int a = 0;
+        if (g.opt.tree == AUTO)
+            a = g.opt.auto_a > 0 ? g.opt.auto_a : auto_domain(u, v, g.opt.workgroups, g.opt.gamma);
+        g.auto_a_used.push_back(a);
+        for (const Elim& e : step_tree(g.opt.tree, u, a)) eliminate(s, e);
+        ensure_tri(s, 0);
+    }
+
+    // QR(p,q) with the Greedy tree over all columns at once (used by
+    // R-BiDiag).  Synchronous rounds: in column j the rows already zeroed in
+    // column j-1 but not yet in column j are candidates; the bottom half of
+    // them is eliminated (TT) by the rows just above.
+    void greedy_qr(int pend) {
+        std::vector<StepState> cols;
+        for (int j = 0; j < q; ++j) cols.push_back(make_step(0, j, j, pend, j + 1, q));
+        for (int j = 0; j < q; ++j) g.auto_a_used.push_back(0);
+        std::vector<int> nz(q, 0);
+        for (;;) {
+            std::vector<int> nzn = nz;
+            bool any = false;
+            for (int j = 0; j < q; ++j) {
+                int top = (j == 0) ? 0 : pend - nz[j - 1];
+                top = std::max(top, j);
+                int bottom = pend - nz[j];
+                int z = bottom - top;
+                int e = z / 2;
+                for (int t = 0; t < e; ++t) {
+                    int i = bottom - 1 - t;
+                    eliminate(cols[j], Elim{i - j, i - e - j, 1});
+                }
+                nzn[j] += e;
+                if (e > 0) any = true;
+            }
+            nz = nzn;
+            if (!any) break;
+        }
+        for (int j = 0; j < q; ++j) ensure_tri(cols[j], 0);
+    }
+};
+
+}  // namespace
+
+std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g) {
+    if (q < 1 || p < q) return "tile grid must satisfy p >= q >= 1";
+    if (opt.tree < FLATTS || opt.tree > AUTO) return "unknown tree";
+    if (opt.variant < BIDIAG || opt.variant > QRONLY) return "unknown variant";
+    g = Graph();
+    g.p = p;
+    g.q = q;
+    g.opt = opt;
+    Builder b(g, p, q);
+    if (opt.variant == BIDIAG) {
+        for (int k = 0; k < q; ++k) {
+            b.run_step(0, k, k, p, k + 1, q);                 // QR(k)
+            if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, p);  // LQ(k)
+        }
+    } else {
+        if (opt.tree == GREEDY) {
+            b.greedy_qr(p);
+        } else {
+            for (int k = 0; k < q; ++k) b.run_step(0, k, k, p, k + 1, q);
+        }
+        if (opt.variant == QRONLY) return std::string();
+        for (int k = 0; k < q; ++k) {
+            if (k > 0) b.run_step(0, k, k, q, k + 1, q);       // QR(k) on the top q x q
+            if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, q);  // LQ(k)
+        }
+    }
+    return std::string();
+}
+
+double critical_path(const Graph& g, const double* w) {
+    std::vector<double> fin(g.tasks.size(), 0.0);
+    double best = 0.0;
+    for (size_t t = 0; t < g.tasks.size(); ++t) {
+        double s = 0.0;
+        for (int32_t pr : g.pred[t]) s = std::max(s, fin[pr]);
+        fin[t] = s + w[g.tasks[t].kind];
+        best = std::max(best, fin[t]);
+    }
+    return best;
+}
+
+}  // namespace bb
