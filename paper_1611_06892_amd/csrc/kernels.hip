@@ -406,7 +406,7 @@ __device__ void update(const KArgs& a, const DevTask& tk, int part, double* lds)
 
 template <int NB>
 __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds) {
-    const DevTask tk = a.tasks[task];
+    const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
     if (tk.kind <= K_TTQRT) panel<NB>(a, tk, lds);
     else update<NB>(a, tk, part, lds);
 }
@@ -441,9 +441,16 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
             s_stop = 0;
         }
         __syncthreads();
-        const int u = s_unit;
+        // The ticket is the same for every thread; readfirstlane makes that
+        // visible to the compiler so the loop exits stay uniform.  (With
+        // exits it must treat as divergent, the loop is restructured so that
+        // lanes other than 0 re-enter the top barrier before lane 0 fetched
+        // the next ticket.)
+        const int u = __builtin_amdgcn_readfirstlane(s_unit);
         if (u >= a.nunits) break;
-        const int2 un = a.units[u];
+        const int2 un0 = a.units[u];
+        const int2 un = make_int2(__builtin_amdgcn_readfirstlane(un0.x),
+                                  __builtin_amdgcn_readfirstlane(un0.y));
         if (tid == 0) {
             const uint64_t t0 = wall_clock64();
             for (;;) {
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
             }
         }
         __syncthreads();
-        if (s_stop) break;
+        if (__builtin_amdgcn_readfirstlane(s_stop)) break;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         run_unit<NB>(a, un.x, un.y, lds);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -473,6 +480,7 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
                 __hip_atomic_fetch_add(&a.deps[a.succ_idx[s]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&a.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        __syncthreads();
     }
 }
 
