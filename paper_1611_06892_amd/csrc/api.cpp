@@ -181,7 +181,7 @@ size_t ws_bytes_of(const bb_plan& P) {
 }
 
 size_t vt_bytes_of(const bb_plan& P) {
-    return (size_t)P.g.nslots * 3 * (size_t)P.nb * P.nb * sizeof(double);
+    return (size_t)P.g.nslots * (size_t)bbk::record_doubles(P.nb) * sizeof(double);
 }
 
 // Upload the graph and schedule to the current device (once per plan).
@@ -392,7 +392,7 @@ int bb_execute(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void
     a.m = P->m;
     a.n = P->n;
     a.vt = (double*)vt;
-    a.slot_stride = 3 * (int64_t)P->nb * P->nb;
+    a.slot_stride = bbk::record_doubles(P->nb);
     char* blob = (char*)P->dblob;
     a.tasks = (const bbk::DevTask*)(blob + P->off_tasks);
     a.nunits = (int32_t)(P->units_ticket.size() / 2);

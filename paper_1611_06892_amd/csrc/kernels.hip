@@ -16,10 +16,11 @@
 // of a panel are kept in compact WY form Q = H_1 ... H_k = I - V T V^T with T
 // upper triangular, and an update applies Q^T: C <- C - V T^T V^T C.
 //
-// One workgroup of 256 threads (4 wave64) executes one work unit.  Panels keep
-// the tile in LDS and run one Householder step per column; updates are three
-// FP64 MFMA contractions (v_mfma_f64_16x16x4) over a column strip of the
-// trailing tile(s), with the strip staged in LDS.
+// One workgroup of 256 threads (4 wave64) executes one work unit.  Panels are
+// blocked by 16 columns (a register-resident leaf plus MFMA trailing updates);
+// updates apply the 16-column blocks of a panel's reflectors with FP64 MFMA
+// (v_mfma_f64_16x16x4) to register-resident 16-column slices of the trailing
+// tile(s).
 #include "kernels.hpp"
 
 namespace bbk {
@@ -33,24 +34,19 @@ enum : int { K_GEQRT = 0, K_TSQRT = 1, K_TTQRT = 2, K_UNMQR = 3, K_TSMQR = 4, K_
 
 template <int NB>
 struct Shape {
-    static constexpr int LDX = NB + 1;                 // odd LDS stride: column walks hit distinct banks
-    static constexpr int NS = NB >= 64 ? 64 : NB;      // update strip width
-    static constexpr int PANEL = NB * LDX + 3 * NB + 8;
-    static constexpr int UPD = 2 * NS * LDX;
-    static constexpr int LDS = PANEL > UPD ? PANEL : UPD;   // doubles
+    static constexpr int MT = NB / 16;                 // 16 x 16 tiles per tile side
+    static constexpr int LDL = NB + 1;                 // LDS stride of the leaf (odd: conflict-free)
+    static constexpr int PANEL = 16 * LDL + 2 * NB + 16 + 512;   // doubles used by a panel
+    static constexpr int UPDATE = 2 * (16 * LDL + 256);           // ... and by an update
+    static constexpr int LDS = PANEL > UPDATE ? PANEL : UPDATE;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Keeps the scheduler from hoisting loads of later 16-row steps of a fully
+// unrolled product above this point (bounds register pressure).
+#define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // A tile seen in the logical frame.  vr/vc: logical rows/columns that exist in
@@ -61,6 +57,12 @@ struct TileView {
     int trans, vr, vc;
     __device__ __forceinline__ double* ptr(int r, int c) const {
         return trans ? base + c + (int64_t)r * ld : base + r + (int64_t)c * ld;
+    }
+    __device__ __forceinline__ double get(int r, int c) const {
+        return (r < vr && c < vc) ? *ptr(r, c) : 0.0;
+    }
+    __device__ __forceinline__ void put(int r, int c, double v) const {
+        if (r < vr && c < vc) *ptr(r, c) = v;
     }
 };
 
@@ -76,339 +78,390 @@ __device__ __forceinline__ TileView view(const KArgs& a, int pr, int pc, int tra
     return t;
 }
 
-// Copy logical columns [c0, c0+W) of a tile into LDS (column-major, stride ld),
-// zero-filling the padding.  The thread-to-element map follows the physical
-// layout so global accesses are contiguous for both frames.
-template <int NB, int W>
-__device__ __forceinline__ void load_block(const TileView& t, int c0, double* s, int ld) {
-    const int tid = threadIdx.x;
-    if (!t.trans) {
-        for (int e = tid; e < NB * W; e += NT) {
-            int r = e % NB, c = e / NB;
-            s[r + c * ld] = (r < t.vr && c0 + c < t.vc) ? *t.ptr(r, c0 + c) : 0.0;
-        }
-    } else {
-        for (int e = tid; e < NB * W; e += NT) {
-            int c = e % W, r = e / W;
-            s[r + c * ld] = (r < t.vr && c0 + c < t.vc) ? *t.ptr(r, c0 + c) : 0.0;
-        }
-    }
+// Register ("accumulator") layout of a 16-column slice of a tile, shared by
+// every MFMA of this file: element r (0..3) of lane l of row tile i holds
+// logical (16 i + 4 r + l/16, c0 + l%16).  That is the result layout of
+// v_mfma_f64_16x16x4, and element r of row tile i is also exactly the second
+// operand of the k-step covering rows 16 i + 4 r .. 16 i + 4 r + 3, so a slice
+// held this way feeds the next product without any data movement.
+template <int MT>
+__device__ __forceinline__ void load_slice(const TileView& t, int c0, d4 (&x)[MT]) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[i][r] = t.get(16 * i + 4 * r + g, c0 + j);
 }
 
-// Store (mode 0), or subtract from memory (mode 1), an LDS block into logical
-// columns [c0, c0+W) of a tile; padding is skipped.
-template <int NB, int W, int MODE>
-__device__ __forceinline__ void store_block(const TileView& t, int c0, const double* s, int ld) {
-    const int tid = threadIdx.x;
-    if (!t.trans) {
-        for (int e = tid; e < NB * W; e += NT) {
-            int r = e % NB, c = e / NB;
-            if (r < t.vr && c0 + c < t.vc) {
-                double* g = t.ptr(r, c0 + c);
-                *g = MODE ? *g - s[r + c * ld] : s[r + c * ld];
-            }
-        }
-    } else {
-        for (int e = tid; e < NB * W; e += NT) {
-            int c = e % W, r = e / W;
-            if (r < t.vr && c0 + c < t.vc) {
-                double* g = t.ptr(r, c0 + c);
-                *g = MODE ? *g - s[r + c * ld] : s[r + c * ld];
-            }
-        }
+template <int MT>
+__device__ __forceinline__ void store_slice(const TileView& t, int c0, const d4 (&x)[MT]) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t.put(16 * i + 4 * r + g, c0 + j, x[i][r]);
+}
+
+__device__ __forceinline__ d4 load16(const TileView& t, int r0, int c0) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    d4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = t.get(r0 + 4 * r + g, c0 + j);
+    return x;
+}
+
+__device__ __forceinline__ void store16(const TileView& t, int r0, int c0, d4 x) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t.put(r0 + 4 * r + g, c0 + j, x[r]);
+}
+
+// Reads of one V/T record through a buffer descriptor: every load of a
+// product shares one per-lane byte offset and adds a wave-uniform constant,
+// so unrolled products need no per-load address registers.  Reads past the
+// record's end return zero.
+struct Rec {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ Rec(const double* base, int nb) {
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0,
+                                                 (int)(8 * (2 * nb * nb + 16 * nb)), 0x00020000);
     }
+    __device__ __forceinline__ double ld(int voff, int soff) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0));
+    }
+};
+
+// Cross-lane move inside rows of 16 lanes (DPP), on both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// Sum over the 16 lanes of a DPP row (lanes l with equal l/16): swap with
+// lane^1 and lane^2 (quad permutes), then with the mirrored lane in the half
+// row and in the row.  Every lane ends with the same bits (each step adds two
+// equal partial sums in either order).  All 16 lanes of the row must be active.
+__device__ __forceinline__ double sum16(double v) {
+    v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);    // row_half_mirror
+    v += dpp<0x140>(v);    // row_mirror
+    return v;
 }
 
 // ---------------------------------------------------------------------------
-// Panel kernels: GEQRT (kind 0), TSQRT (1), TTQRT (2).
+// Panel kernels: GEQRT, TSQRT, TTQRT (Table 1), blocked by 16 columns.
 //
-// GEQRT factors tile X = T1: R overwrites its upper triangle, zeros below;
-// V (unit lower triangular) goes to the task's record.  TSQRT/TTQRT factor
-// [R1; X2] with R1 = T1 upper triangular and X2 = T2 square (TS) or upper
-// triangular (TT): R1 is updated in place, X2 is zeroed, and V holds the lower
-// parts of the reflectors (their upper parts are unit vectors e_c), which is
-// full for TS and upper triangular for TT.
+// GEQRT factors the tile X = T1 (R overwrites its upper triangle, zeros below).
+// TSQRT / TTQRT factor [R1; X2] with R1 = T1 upper triangular and X2 = T2
+// square (TS) or upper triangular (TT): R1 is updated in place and X2 zeroed.
+// The reflector of column c is u_c = e_c + (tail below the diagonal) for
+// GEQRT and u_c = [e_c ; v2_c] for TS/TT; V stores the tails (with the unit
+// diagonal made explicit for GEQRT), which are full for TS and upper
+// triangular for TT.
 //
-// Record layout (FP64, column-major, nb x nb each): V, V^T, T^T.
-// T is formed from G = V^T V (strictly upper part, accumulated while the
-// panel is factored, from the dot products of the reflector of column c with
-// the finished columns j < c) by the forward recurrence
-//   T(c,c) = tau_c,   T(0:c-1, c) = -tau_c T(0:c-1, 0:c-1) G(0:c-1, c),
-// evaluated row by row: row i of T depends only on row i and on G.
+// Columns are processed in blocks of 16 (the paper's inner blocking ib):
+//  1. leaf: the 16 columns of block b are factored one column at a time by
+//     all 256 threads (thread (c, q) holds rows q, q+16, ... of leaf column c
+//     in registers; one barrier per column).  The dot products of each new
+//     reflector with the finished ones give G_b = U_b^T U_b, from which
+//     T_b (16 x 16 upper, Q_b = I - U_b T_b U_b^T) follows by the forward
+//     recurrence T(c,c) = tau_c, T(0:c-1,c) = -tau_c T(0:c-1,0:c-1) G(0:c-1,c).
+//  2. trailing: Q_b^T is applied to the column tiles right of the block with
+//     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W).
+//     Column tile J lives in registers of wave J % 4 for the whole kernel.
+// Record (FP64): V (nb x nb, column-major), V^T (column-major), then the
+// nb/16 blocks T_b^T (16 x 16 column-major) -- the same blocked compact-WY
+// form the update kernels apply.
 // ---------------------------------------------------------------------------
-template <int NB>
-__device__ void panel(const KArgs& a, const DevTask& tk, double* lds) {
+template <int NB, int KIND>
+__device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds) {
     using S = Shape<NB>;
-    constexpr int LDX = S::LDX;
-    constexpr int TPC = NT / NB;           // threads per column
-    static_assert(NT % NB == 0 && TPC <= 64, "tile size");
-    double* X = lds;
-    double* tau = X + NB * LDX;
-    double* rrow = tau + NB;               // two buffers of NB: R1 rows c and c+1
-    double* sh = rrow + 2 * NB;
-    const int tid = threadIdx.x;
-    const bool pair = tk.kind != K_GEQRT;
-    const bool tt = tk.kind == K_TTQRT;
+    constexpr int MT = S::MT, LDL = S::LDL;
+    constexpr int OWN = (MT + 3) / 4;       // column tiles per wave
+    constexpr int SR = NB / 16;             // leaf rows per thread
+    constexpr bool PAIR = KIND != K_GEQRT;
+    constexpr bool TT = KIND == K_TTQRT;
+    double* Lf = lds;                       // leaf: NB x 16, stride LDL
+    double* vbuf = Lf + 16 * LDL;           // 2 x NB: broadcast of the current reflector
+    double* taus = vbuf + 2 * NB;           // 16
+    double* Gs = taus + 16;                 // G(l, c) at l + 16 c
+    double* TbT = Gs + 256;                 // T(k, i) at i + 16 k
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
+    const int lj = tid >> 4, lq = tid & 15; // leaf column, row phase
 
     const TileView T1 = view(a, tk.r1, tk.c1, tk.trans, NB);
-    TileView T2 = T1;
-    if (pair) T2 = view(a, tk.r2, tk.c2, tk.trans, NB);
+    const TileView TX = PAIR ? view(a, tk.r2, tk.c2, tk.trans, NB) : T1;
     double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
     double* gV = rec;
     double* gVt = rec + NB * NB;
-    double* gTt = rec + 2 * NB * NB;       // holds G during the factorization
+    double* gTt = rec + 2 * NB * NB;
 
-    load_block<NB, NB>(pair ? T2 : T1, 0, X, LDX);
-    if (pair)
-        for (int jj = tid; jj < NB; jj += NT) rrow[jj] = (0 < T1.vr && jj < T1.vc) ? *T1.ptr(0, jj) : 0.0;
-    __syncthreads();
+    d4 xt[OWN][MT];
+#pragma unroll
+    for (int o = 0; o < OWN; ++o)
+        if (w + 4 * o < MT) load_slice<MT>(TX, 16 * (w + 4 * o), xt[o]);
 
-    const int j = tid / TPC, h = tid % TPC;
-    for (int c = 0; c < NB; ++c) {
-        double* rr = rrow + (c & 1) * NB;
-        const int vlo = pair ? 0 : c + 1;      // rows of X holding the reflector's tail
-        const int vhi = tt ? c + 1 : NB;
-        if (tid < 64) {
-            double ss = 0.0;
-            for (int r = vlo + tid; r < vhi; r += 64) {
-                double x = X[r + c * LDX];
-                ss += x * x;
-            }
-            ss = wave_sum(ss);
-            if (tid == 0) {
-                double alpha = pair ? rr[c] : X[c + c * LDX];
-                double t = 0.0, beta = alpha, scale = 0.0;
+    for (int b = 0; b < MT; ++b) {
+        // Column tile b goes to the leaf buffer.
+        if (w == (b & 3)) {
+#pragma unroll
+            for (int o = 0; o < OWN; ++o)
+                if (o == (b >> 2)) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Lf[(16 * i + 4 * r + g) + j * LDL] = xt[o][i][r];
+                }
+        }
+        Gs[tid] = 0.0;
+        __syncthreads();
+
+        // 1. Leaf.
+        double x[SR];
+#pragma unroll
+        for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
+        double r1 = 0.0;                    // PAIR: R1(16b + lq, 16b + lj)
+        if (PAIR) r1 = T1.get(16 * b + lq, 16 * b + lj);
+        for (int c = 0; c < 16; ++c) {
+            const int cc = 16 * b + c;
+            double* vb = vbuf + (c & 1) * NB;
+            if (lj == c) {
+                double ss = 0.0, al = 0.0;
+#pragma unroll
+                for (int s = 0; s < SR; ++s) {
+                    const int row = lq + 16 * s;
+                    const bool tail = PAIR ? (!TT || row <= cc) : row > cc;
+                    if (tail) ss += x[s] * x[s];
+                    if (!PAIR && row == cc) al = x[s];
+                }
+                if (PAIR && lq == c) al = r1;
+                ss = sum16(ss);
+                al = sum16(al);
+                double tau = 0.0, beta = al, scale = 0.0;
                 if (ss != 0.0) {
-                    double nrm = hypot(alpha, sqrt(ss));
-                    beta = alpha >= 0.0 ? -nrm : nrm;
-                    t = (beta - alpha) / beta;
-                    scale = 1.0 / (alpha - beta);
+                    const double nrm = sqrt(fma(al, al, ss));
+                    beta = al >= 0.0 ? -nrm : nrm;
+                    tau = (beta - al) / beta;
+                    scale = 1.0 / (al - beta);
                 }
-                tau[c] = t;
-                sh[0] = scale;
-                if (pair) rr[c] = beta; else X[c + c * LDX] = beta;
-            }
-        }
-        if (pair && c + 1 < NB) {              // prefetch R1 row c+1 (untouched by step c)
-            double* rn = rrow + ((c + 1) & 1) * NB;
-            for (int jj = tid; jj < NB; jj += NT)
-                if (jj >= c + 1) rn[jj] = (c + 1 < T1.vr && jj < T1.vc) ? *T1.ptr(c + 1, jj) : 0.0;
-        }
-        __syncthreads();
-        const double tc = tau[c];
-        if (tc != 0.0) {
-            const double scale = sh[0];
-            for (int r = vlo + tid; r < vhi; r += NT) X[r + c * LDX] *= scale;
-        }
-        __syncthreads();
-        if (tc != 0.0 && j != c) {
-            double d = 0.0;
-            if (h == 0) d = (j > c) ? (pair ? rr[j] : X[c + j * LDX]) : (pair ? 0.0 : X[c + j * LDX]);
-            for (int r = vlo + h; r < vhi; r += TPC) d += X[r + c * LDX] * X[r + j * LDX];
-            d = group_sum<TPC>(d);
-            if (j > c) {
-                const double w = tc * d;
-                for (int r = vlo + h; r < vhi; r += TPC) X[r + j * LDX] -= w * X[r + c * LDX];
-                if (h == 0) {
-                    if (pair) rr[j] -= w; else X[c + j * LDX] -= w;
+#pragma unroll
+                for (int s = 0; s < SR; ++s) {
+                    const int row = lq + 16 * s;
+                    double vv;
+                    if (PAIR) {
+                        const bool tail = !TT || row <= cc;
+                        if (tail) x[s] *= scale;
+                        vv = tail ? x[s] : 0.0;
+                    } else {
+                        if (row > cc) x[s] *= scale;
+                        if (row == cc) x[s] = beta;
+                        vv = row > cc ? x[s] : (row == cc ? 1.0 : 0.0);
+                    }
+                    vb[row] = vv;
                 }
-            } else if (h == 0) {
-                gTt[j + c * NB] = d;           // G(j, c) = u_j . u_c
+                if (PAIR && lq == c) r1 = beta;
+                if (lq == 0) taus[c] = tau;
+            }
+            __syncthreads();
+            const double tc = taus[c];
+            if (tc != 0.0 && lj != c) {
+                double vv[SR], d = 0.0;
+#pragma unroll
+                for (int s = 0; s < SR; ++s) {
+                    vv[s] = vb[lq + 16 * s];
+                    d += vv[s] * x[s];
+                }
+                if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                d = sum16(d);
+                if (lj > c) {
+                    const double wv = tc * d;
+#pragma unroll
+                    for (int s = 0; s < SR; ++s) x[s] -= wv * vv[s];
+                    if (PAIR && lq == c) r1 -= wv;
+                } else if (lq == 0) {
+                    Gs[lj + 16 * c] = d;                // u_lj . u_c
+                }
             }
         }
         __syncthreads();
-        if (pair)
-            for (int jj = tid; jj < NB; jj += NT)
-                if (jj >= c && c < T1.vr && jj < T1.vc) *T1.ptr(c, jj) = rr[jj];
-    }
-    __syncthreads();
 
-    // Outputs: R / zeros into the matrix, V and V^T into the record.
-    if (!pair) {
-        for (int e = tid; e < NB * NB; e += NT) {
-            int r = e % NB, c = e / NB;
-            double x = X[r + c * LDX];
-            gV[r + c * NB] = r > c ? x : (r == c ? 1.0 : 0.0);
-        }
-        for (int e = tid; e < NB * NB; e += NT) {
-            int c = e % NB, r = e / NB;        // V^T(c, r) = V(r, c)
-            double x = X[r + c * LDX];
-            gVt[c + r * NB] = r > c ? x : (r == c ? 1.0 : 0.0);
-        }
-        // R into T1 (logical upper triangle, zeros below), masked by the padding.
-        if (!T1.trans) {
-            for (int e = tid; e < NB * NB; e += NT) {
-                int r = e % NB, c = e / NB;
-                if (r < T1.vr && c < T1.vc) *T1.ptr(r, c) = r <= c ? X[r + c * LDX] : 0.0;
+        // T_b by rows (row i depends on itself and on G only).
+        if (tid < 16) {
+            const int i = tid;
+            double tr[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double tcv = taus[c];
+                double sacc = 0.0;
+#pragma unroll
+                for (int l = 0; l < c; ++l)
+                    if (l >= i) sacc += tr[l] * Gs[l + 16 * c];
+                tr[c] = c < i ? 0.0 : (c == i ? tcv : (tcv == 0.0 ? 0.0 : -tcv * sacc));
+                SCHED_FENCE();
             }
-        } else {
-            for (int e = tid; e < NB * NB; e += NT) {
-                int c = e % NB, r = e / NB;
-                if (r < T1.vr && c < T1.vc) *T1.ptr(r, c) = r <= c ? X[r + c * LDX] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                TbT[c + 16 * i] = tr[c];
+                gTt[256 * b + c + 16 * i] = tr[c];
             }
         }
-    } else {
-        for (int e = tid; e < NB * NB; e += NT) {
-            int r = e % NB, c = e / NB;
-            gV[r + c * NB] = (tt && r > c) ? 0.0 : X[r + c * LDX];
-        }
-        for (int e = tid; e < NB * NB; e += NT) {
-            int c = e % NB, r = e / NB;
-            gVt[c + r * NB] = (tt && r > c) ? 0.0 : X[r + c * LDX];
-        }
-        if (!T2.trans) {
-            for (int e = tid; e < NB * NB; e += NT) {
-                int r = e % NB, c = e / NB;
-                if (r < T2.vr && c < T2.vc) *T2.ptr(r, c) = 0.0;
+        // Leaf outputs: explicit U_b tails into the leaf buffer and the record,
+        // R (GEQRT) or zeros (TS/TT) into the matrix.
+        {
+            const int col = 16 * b + lj;
+#pragma unroll
+            for (int s = 0; s < SR; ++s) {
+                const int row = lq + 16 * s;
+                double vv;
+                if (PAIR) vv = (TT && row > col) ? 0.0 : x[s];
+                else vv = row > col ? x[s] : (row == col ? 1.0 : 0.0);
+                Lf[row + lj * LDL] = vv;
+                gV[row + (int64_t)col * NB] = vv;
+                gVt[col + (int64_t)row * NB] = vv;
+                TX.put(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
             }
-        } else {
-            for (int e = tid; e < NB * NB; e += NT) {
-                int c = e % NB, r = e / NB;
-                if (r < T2.vr && c < T2.vc) *T2.ptr(r, c) = 0.0;
-            }
+            if (PAIR) T1.put(16 * b + lq, 16 * b + lj, r1);
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // T from G: packed strictly-upper G and packed upper T share the X area.
-    double* Gp = X;                          // G(l, c), l < c  at c(c-1)/2 + l
-    double* Tp = X + NB * (NB - 1) / 2;      // T(i, c), i <= c at c(c+1)/2 + i
-    for (int e = tid; e < NB * NB; e += NT) {
-        int l = e % NB, c = e / NB;
-        if (l < c) Gp[c * (c - 1) / 2 + l] = tau[c] != 0.0 ? gTt[l + c * NB] : 0.0;
-    }
-    __syncthreads();
-    {
-        constexpr int TPR = NT / NB;         // threads per row of T
-        const int i = tid / TPR, hh = tid % TPR;
-        if (hh == 0) Tp[i * (i + 1) / 2 + i] = tau[i];
-        for (int c = i + 1; c < NB; ++c) {
-            double s = 0.0;
-            for (int l = i + hh; l < c; l += TPR) s += Tp[l * (l + 1) / 2 + i] * Gp[c * (c - 1) / 2 + l];
-            s = group_sum<TPR>(s);
-            if (hh == 0) Tp[c * (c + 1) / 2 + i] = -tau[c] * s;
-            // the other lanes of the group read T(i, c) in later iterations;
-            // LDS operations of one wave complete in order.
+        // 2. Trailing update of the column tiles right of block b.
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int J = w + 4 * o;
+            if (J < MT && J > b) {
+                d4 R1b = {0.0, 0.0, 0.0, 0.0};
+                if (PAIR) R1b = load16(T1, 16 * b, 16 * J);
+                d4 W = R1b;
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    if (!PAIR && i < b) continue;
+                    if (TT && i > b) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) W = mfma(Lf[(16 * i + 4 * r + g) + j * LDL], xt[o][i][r], W);
+                    SCHED_FENCE();
+                }
+                d4 W2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
+                if (PAIR) store16(T1, 16 * b, 16 * J, R1b - W2);
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    if (!PAIR && i < b) continue;
+                    if (TT && i > b) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        xt[o][i] = mfma(-Lf[(16 * i + j) + (4 * r + g) * LDL], W2[r], xt[o][i]);
+                    SCHED_FENCE();
+                }
+            }
         }
-    }
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += NT) {
-        int c = e % NB, i = e / NB;           // T^T(c, i) = T(i, c)
-        gTt[c + i * NB] = i <= c ? Tp[c * (c + 1) / 2 + i] : 0.0;
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Update kernels: UNMQR (kind 3), TSMQR (4), TTMQR (5), on the logical column
-// strip [c0, c0+NS) of the trailing tile(s):
-//   W  = C1 + V^T C2          (C1 absent for UNMQR: W = V^T C)
-//   W  = T^T W
-//   C1 = C1 - W ,  C2 = C2 - V W
-// The three products run on v_mfma_f64_16x16x4.  Operand layouts of that
-// instruction (wave64): A (16x4) lane l holds A(l%16, l/16); B (4x16) lane l
-// holds B(l/16, l%16); result element r (0..3) of lane l is D(4r + l/16, l%16).  The first operand comes straight from the record (V, V^T, T^T
-// are stored so that 16 consecutive lanes read 16 consecutive doubles); the
-// second from the LDS copy of the strip.
+// Update kernels: UNMQR, TSMQR, TTMQR (Table 1) on the logical column strip
+// [64 part, 64 part + 64) of the trailing tile(s) (32 columns when nb = 32).
+// Wave w owns the 16 columns 64 part + 16 w .. + 15 of C2 (and C1) and applies
+// the nb/16 blocks of the record in order (block b+1 is fetched from memory
+// while block b is applied, then staged in LDS for all four waves):
+//   W = C1(block-row b) + V_b^T C2     (UNMQR: no C1)
+//   W = T_b^T W
+//   C1(block-row b) -= W,   C2 -= V_b W
+// which is Q^T [C1; C2] for Q = Q_0 Q_1 ... (Section 3.2).  Zero 16 x 16
+// blocks of V are skipped: V is unit lower triangular after GEQRT and upper
+// triangular after TTQRT.
 // ---------------------------------------------------------------------------
-template <int NB>
-__device__ void update(const KArgs& a, const DevTask& tk, int part, double* lds) {
-    using S = Shape<NB>;
-    constexpr int NS = S::NS, LD = S::LDX;
-    constexpr int MT = NB / 16, NTL = NS / 16;
-    constexpr int WR = MT >= 4 ? 4 : MT, WC = 4 / WR;
-    constexpr int RPW = MT / WR, CPW = NTL / WC;
-    static_assert(WR * WC == 4 && RPW * WR == MT && CPW * WC == NTL, "wave tiling");
-    double* Cs = lds;               // C2 strip, NB x NS
-    double* Ws = lds + NS * LD;     // C1 strip, then W
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const int c0 = part * NS;
-    const bool hasC1 = tk.kind != K_UNMQR;
-
+template <int NB, int KIND>
+__device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds) {
+    constexpr int MT = NB / 16;
+    constexpr int NS = NB >= 64 ? 64 : NB;
+    constexpr int LDV = NB + 1;
+    constexpr int BUF = 16 * LDV + 256;       // V_b (NB x 16, stride LDV) then T_b^T (16 x 16)
+    constexpr int PRE = NB / 16 + 1;          // staged doubles per thread and block
+    constexpr bool HASC1 = KIND != K_UNMQR;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
+    const int c0 = part * NS + 16 * w;
     const TileView T2 = view(a, tk.r2, tk.c2, tk.trans, NB);
-    if (c0 >= T2.vc) return;                  // strip lies in the padding: nothing to do
-    TileView T1 = T2;
-    if (hasC1) T1 = view(a, tk.r1, tk.c1, tk.trans, NB);
+    const TileView T1 = HASC1 ? view(a, tk.r1, tk.c1, tk.trans, NB) : T2;
+    // Waves without columns still take part in staging and barriers.
+    const bool active = 16 * w < NS && c0 < T2.vc;
+    const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
 
-    load_block<NB, NS>(T2, c0, Cs, LD);
-    if (hasC1) {
-        load_block<NB, NS>(T1, c0, Ws, LD);
-    } else {
-        for (int e = tid; e < NB * NS; e += NT) Ws[(e % NB) + (e / NB) * LD] = 0.0;
-    }
-    __syncthreads();
-
-    const double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
-    const double* gV = rec;
-    const double* gVt = rec + NB * NB;
-    const double* gTt = rec + 2 * NB * NB;
-    const int row0 = (w % WR) * RPW * 16, col0 = (w / WR) * CPW * 16;
-    const int li = lane & 15, lk = lane >> 4;
-    d4 acc[RPW][CPW];
-
-    auto load_acc = [&](const double* src) {
+    // Block b of the record: V(:, 16b..16b+15) is contiguous (column-major),
+    // T_b^T follows the two nb x nb matrices.  Thread t stages elements t + 256k.
+    auto fetch = [&](int b, double (&pre)[PRE]) {
 #pragma unroll
-        for (int ri = 0; ri < RPW; ++ri)
-#pragma unroll
-            for (int ci = 0; ci < CPW; ++ci)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc[ri][ci][r] = src[(row0 + ri * 16 + 4 * r + lk) + (col0 + ci * 16 + li) * LD];
+        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
+        pre[PRE - 1] = rec.ld(8 * tid, 8 * (2 * NB * NB + 256 * b));
     };
-    auto store_acc = [&](double* dst) {
+    auto stage = [&](int b, const double (&pre)[PRE]) {
+        double* buf = lds + (b & 1) * BUF;
 #pragma unroll
-        for (int ri = 0; ri < RPW; ++ri)
-#pragma unroll
-            for (int ci = 0; ci < CPW; ++ci)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    dst[(row0 + ri * 16 + 4 * r + lk) + (col0 + ci * 16 + li) * LD] = acc[ri][ci][r];
-    };
-    // acc += sign * A(rows, k) * Bs(k, cols), A(i, k) = gA[i + k NB], Bs from LDS.
-    auto gemm = [&](const double* gA, const double* Bs, double sign) {
-        for (int k = 0; k < NB; k += 4) {
-            double av[RPW], bv[CPW];
-#pragma unroll
-            for (int ri = 0; ri < RPW; ++ri) av[ri] = sign * gA[(row0 + ri * 16 + li) + (k + lk) * NB];
-#pragma unroll
-            for (int ci = 0; ci < CPW; ++ci) bv[ci] = Bs[(k + lk) + (col0 + ci * 16 + li) * LD];
-#pragma unroll
-            for (int ri = 0; ri < RPW; ++ri)
-#pragma unroll
-                for (int ci = 0; ci < CPW; ++ci)
-                    acc[ri][ci] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ri], bv[ci], acc[ri][ci], 0, 0, 0);
+        for (int k = 0; k < PRE - 1; ++k) {
+            const int e = tid + 256 * k;
+            buf[(e % NB) + (e / NB) * LDV] = pre[k];
         }
+        buf[16 * LDV + tid] = pre[PRE - 1];
     };
 
-    // W = C1 + V^T C2   (A operand V^T(i, k) = gVt[i + k NB])
-    load_acc(Ws);
-    gemm(gVt, Cs, 1.0);
-    store_acc(Ws);                            // each wave owns its block of Ws
+    d4 c2[MT];
+    if (active) load_slice<MT>(T2, c0, c2);
+    double pre[PRE];
+    fetch(0, pre);
+    stage(0, pre);
+    d4 C1n = {0.0, 0.0, 0.0, 0.0};
+    if (HASC1 && active) C1n = load16(T1, 0, c0);
     __syncthreads();
-    // W = T^T W
 #pragma unroll
-    for (int ri = 0; ri < RPW; ++ri)
+    for (int b = 0; b < MT; ++b) {
+        const double* Vs = lds + (b & 1) * BUF;
+        const double* Ts = Vs + 16 * LDV;
+        if (b + 1 < MT) fetch(b + 1, pre);
+        const d4 C1b = C1n;
+        if (HASC1 && active && b + 1 < MT) C1n = load16(T1, 16 * (b + 1), c0);
+        if (active) {
+            d4 W = C1b;
 #pragma unroll
-        for (int ci = 0; ci < CPW; ++ci) acc[ri][ci] = d4{0.0, 0.0, 0.0, 0.0};
-    gemm(gTt, Ws, 1.0);
-    __syncthreads();
-    store_acc(Ws);
-    __syncthreads();
-    // C1 -= W
-    if (hasC1) store_block<NB, NS, 1>(T1, c0, Ws, LD);
-    // C2 = C2 - V W
-    load_acc(Cs);
-    gemm(gV, Ws, -1.0);
-    store_acc(Cs);
-    __syncthreads();
-    store_block<NB, NS, 0>(T2, c0, Cs, LD);
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W = mfma(Vs[(16 * i + 4 * r + g) + j * LDV], c2[i][r], W);
+            }
+            d4 W2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) W2 = mfma(Ts[j + 16 * (4 * r + g)], W[r], W2);
+            if (HASC1) store16(T1, 16 * b, c0, C1b - W2);
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c2[i] = mfma(-Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
+            }
+        }
+        if (b + 1 < MT) stage(b + 1, pre);
+        __syncthreads();
+    }
+    if (active) store_slice<MT>(T2, c0, c2);
 }
 
 template <int NB>
 __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds) {
     const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
-    if (tk.kind <= K_TTQRT) panel<NB>(a, tk, lds);
-    else update<NB>(a, tk, part, lds);
+    switch (tk.kind) {
+    case K_GEQRT: panel<NB, K_GEQRT>(a, tk, lds); break;
+    case K_TSQRT: panel<NB, K_TSQRT>(a, tk, lds); break;
+    case K_TTQRT: panel<NB, K_TTQRT>(a, tk, lds); break;
+    case K_UNMQR: update<NB, K_UNMQR>(a, tk, part, lds); break;
+    case K_TSMQR: update<NB, K_TSMQR>(a, tk, part, lds); break;
+    default: update<NB, K_TTMQR>(a, tk, part, lds); break;
+    }
 }
 
 }  // namespace

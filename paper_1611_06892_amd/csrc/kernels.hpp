@@ -18,7 +18,7 @@ struct KArgs {
     double* A;
     int64_t lda, m, n;
     double* vt;              // V/T records
-    int64_t slot_stride;     // doubles per record (3 nb^2)
+    int64_t slot_stride;     // doubles per record (record_doubles(nb))
     const DevTask* tasks;
     const int2* units;       // (task, part) in execution order
     int32_t nunits;
@@ -31,6 +31,9 @@ struct KArgs {
 
 // Update strip width (columns of the logical C tile per work unit).
 inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
+
+// One V/T record: V and V^T (nb x nb each) and nb/16 blocks T_b^T (16 x 16).
+inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
