@@ -45,6 +45,15 @@ struct Shape {
 // unrolled product above this point (bounds register pressure).
 #define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 
+// Workgroup barrier that orders LDS only.  The tile kernels exchange data
+// between waves through LDS alone; their global stores (outputs) are not read
+// back by the same workgroup, so barriers need not wait for them.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -218,7 +227,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 }
         }
         Gs[tid] = 0.0;
-        __syncthreads();
+        lds_barrier();
 
         // 1. Leaf.
         double x[SR];
@@ -230,16 +239,20 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             const int cc = 16 * b + c;
             double* vb = vbuf + (c & 1) * NB;
             if (lj == c) {
-                double ss = 0.0, al = 0.0;
+                double sq[SR], al = 0.0;
 #pragma unroll
                 for (int s = 0; s < SR; ++s) {
                     const int row = lq + 16 * s;
                     const bool tail = PAIR ? (!TT || row <= cc) : row > cc;
-                    if (tail) ss += x[s] * x[s];
+                    sq[s] = tail ? x[s] * x[s] : 0.0;
                     if (!PAIR && row == cc) al = x[s];
                 }
+#pragma unroll
+                for (int h = 1; h < SR; h *= 2)
+#pragma unroll
+                    for (int s = 0; s + h < SR; s += 2 * h) sq[s] += sq[s + h];
                 if (PAIR && lq == c) al = r1;
-                ss = sum16(ss);
+                const double ss = sum16(sq[0]);
                 al = sum16(al);
                 double tau = 0.0, beta = al, scale = 0.0;
                 if (ss != 0.0) {
@@ -266,49 +279,50 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 if (PAIR && lq == c) r1 = beta;
                 if (lq == 0) taus[c] = tau;
             }
-            __syncthreads();
+            lds_barrier();
             const double tc = taus[c];
-            if (tc != 0.0 && lj != c) {
-                double vv[SR], d = 0.0;
+            if (lj != c) {
+                if (tc != 0.0) {
+                    double vv[SR], d = 0.0;
 #pragma unroll
-                for (int s = 0; s < SR; ++s) {
-                    vv[s] = vb[lq + 16 * s];
-                    d += vv[s] * x[s];
-                }
-                if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
-                d = sum16(d);
-                if (lj > c) {
-                    const double wv = tc * d;
+                    for (int s = 0; s < SR; ++s) {
+                        vv[s] = vb[lq + 16 * s];
+                        d = fma(vv[s], x[s], d);
+                    }
+                    if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                    d = sum16(d);
+                    if (lj > c) {
+                        const double wv = tc * d;
 #pragma unroll
-                    for (int s = 0; s < SR; ++s) x[s] -= wv * vv[s];
-                    if (PAIR && lq == c) r1 -= wv;
-                } else if (lq == 0) {
-                    Gs[lj + 16 * c] = d;                // u_lj . u_c
+                        for (int s = 0; s < SR; ++s) x[s] -= wv * vv[s];
+                        if (PAIR && lq == c) r1 -= wv;
+                    } else if (lq == 0) {
+                        Gs[lj + 16 * c] = d;            // u_lj . u_c
+                    }
                 }
             }
         }
-        __syncthreads();
-
-        // T_b by rows (row i depends on itself and on G only).
-        if (tid < 16) {
-            const int i = tid;
-            double tr[16];
+        lds_barrier();
+        // T_b by the forward recurrence T(c,c) = tau_c,
+        // T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c), with thread (i, l) =
+        // (tid/16, tid%16) holding T(i,l): one product and a row sum per column.
+        {
+            const int i = lj, l = lq;
+            double gl[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) gl[c] = Gs[l + 16 * c];
+            double til = 0.0;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 const double tcv = taus[c];
-                double sacc = 0.0;
-#pragma unroll
-                for (int l = 0; l < c; ++l)
-                    if (l >= i) sacc += tr[l] * Gs[l + 16 * c];
-                tr[c] = c < i ? 0.0 : (c == i ? tcv : (tcv == 0.0 ? 0.0 : -tcv * sacc));
-                SCHED_FENCE();
+                const double sm = sum16((l >= i && l < c) ? til * gl[c] : 0.0);
+                const double tic = c < i ? 0.0 : (c == i ? tcv : -tcv * sm);
+                if (l == c) til = tic;
             }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                TbT[c + 16 * i] = tr[c];
-                gTt[256 * b + c + 16 * i] = tr[c];
-            }
+            TbT[l + 16 * i] = til;       // T(i, l)
         }
+        lds_barrier();
+        gTt[256 * b + tid] = ((tid & 15) < (tid >> 4)) ? 0.0 : TbT[tid];
         // Leaf outputs: explicit U_b tails into the leaf buffer and the record,
         // R (GEQRT) or zeros (TS/TT) into the matrix.
         {
@@ -326,7 +340,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             }
             if (PAIR) T1.put(16 * b + lq, 16 * b + lj, r1);
         }
-        __syncthreads();
+        lds_barrier();
 
         // 2. Trailing update of the column tiles right of block b.
 #pragma unroll
@@ -359,7 +373,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -416,7 +430,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     stage(0, pre);
     d4 C1n = {0.0, 0.0, 0.0, 0.0};
     if (HASC1 && active) C1n = load16(T1, 0, c0);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int b = 0; b < MT; ++b) {
         const double* Vs = lds + (b & 1) * BUF;
@@ -425,14 +439,17 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
         const d4 C1b = C1n;
         if (HASC1 && active && b + 1 < MT) C1n = load16(T1, 16 * (b + 1), c0);
         if (active) {
-            d4 W = C1b;
+            // Two accumulators halve the dependent-MFMA chain of W.
+            d4 Wp[2] = {C1b, {0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
                 if (KIND == K_UNMQR && i < b) continue;
                 if (KIND == K_TTMQR && i > b) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W = mfma(Vs[(16 * i + 4 * r + g) + j * LDV], c2[i][r], W);
+                for (int r = 0; r < 4; ++r)
+                    Wp[r & 1] = mfma(Vs[(16 * i + 4 * r + g) + j * LDV], c2[i][r], Wp[r & 1]);
             }
+            const d4 W = Wp[0] + Wp[1];
             d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) W2 = mfma(Ts[j + 16 * (4 * r + g)], W[r], W2);
@@ -446,7 +463,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
             }
         }
         if (b + 1 < MT) stage(b + 1, pre);
-        __syncthreads();
+        lds_barrier();
     }
     if (active) store_slice<MT>(T2, c0, c2);
 }
