@@ -46,6 +46,13 @@ namespace {
 
 const double kUnit[6] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0};   // Table 1
 
+// Execution-cost model used to order work on the GPU (relative latency of one
+// task with its column strips run side by side).  Unlike Table 1, whose unit
+// is flops, it reflects that a panel is a chain of nb dependent Householder
+// steps while an update is throughput-bound MFMA work (measured on MI355X for
+// nb = 128: panels ~110 us, UNMQR / TSMQR / TTMQR strips ~25 / 36 / 30 us).
+const double kGpuCost[6] = {11.0, 11.0, 11.0, 2.5, 3.6, 3.0};
+
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Host validation of a schedule: predecessors precede each task in program
@@ -95,19 +102,17 @@ int build_schedule(bb_plan& P) {
     for (int t = 0; t < nt; ++t)
         for (int32_t pr : g.pred[t]) P.succ_idx[fill[pr]++] = t;
 
-    // Priorities: bottom level (longest weighted path from the task to the end).
+    // Priorities: bottom level (longest path from the task to the end under
+    // the GPU cost model).
     std::vector<double> blevel(nt, 0.0);
     for (int t = nt - 1; t >= 0; --t) {
         double b = 0.0;
         for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) b = std::max(b, blevel[P.succ_idx[s]]);
-        blevel[t] = b + kUnit[g.tasks[t].kind];
+        blevel[t] = b + kGpuCost[g.tasks[t].kind];
     }
-    P.cp = 0.0;
+    P.cp = bb::critical_path(g, kUnit);
     P.total = 0.0;
-    for (int t = 0; t < nt; ++t) {
-        P.cp = std::max(P.cp, blevel[t]);
-        P.total += kUnit[g.tasks[t].kind];
-    }
+    for (int t = 0; t < nt; ++t) P.total += kUnit[g.tasks[t].kind];
 
     // Ticket order: list scheduling of the units on W workers, highest bottom
     // level first; the order in which units start is the ticket order.
@@ -133,7 +138,7 @@ int build_schedule(bb_plan& P) {
             int t = std::get<1>(r);
             P.units_ticket.push_back(t);
             P.units_ticket.push_back(std::get<2>(r));
-            running.emplace(now + kUnit[g.tasks[t].kind] / P.nparts[t], t);
+            running.emplace(now + kGpuCost[g.tasks[t].kind], t);
             busy++;
         }
         if (running.empty()) break;

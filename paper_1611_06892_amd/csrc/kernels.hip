@@ -58,6 +58,16 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Global store of a task output.  CO (coherent outputs) selects agent-scope
+// stores, which are made coherent across the L2s of all XCDs as they
+// complete; the persistent scheduler uses them so that finishing a task needs
+// only a wait for its stores instead of an L2 write-back.
+template <bool CO>
+__device__ __forceinline__ void gstore(double* p, double v) {
+    if (CO) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 // A tile seen in the logical frame.  vr/vc: logical rows/columns that exist in
 // the matrix (the rest of the nb x nb tile is zero padding, never accessed).
 struct TileView {
@@ -70,8 +80,9 @@ struct TileView {
     __device__ __forceinline__ double get(int r, int c) const {
         return (r < vr && c < vc) ? *ptr(r, c) : 0.0;
     }
+    template <bool CO>
     __device__ __forceinline__ void put(int r, int c, double v) const {
-        if (r < vr && c < vc) *ptr(r, c) = v;
+        if (r < vr && c < vc) gstore<CO>(ptr(r, c), v);
     }
 };
 
@@ -102,13 +113,13 @@ __device__ __forceinline__ void load_slice(const TileView& t, int c0, d4 (&x)[MT
         for (int r = 0; r < 4; ++r) x[i][r] = t.get(16 * i + 4 * r + g, c0 + j);
 }
 
-template <int MT>
+template <bool CO, int MT>
 __device__ __forceinline__ void store_slice(const TileView& t, int c0, const d4 (&x)[MT]) {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) t.put(16 * i + 4 * r + g, c0 + j, x[i][r]);
+        for (int r = 0; r < 4; ++r) t.put<CO>(16 * i + 4 * r + g, c0 + j, x[i][r]);
 }
 
 __device__ __forceinline__ d4 load16(const TileView& t, int r0, int c0) {
@@ -119,10 +130,11 @@ __device__ __forceinline__ d4 load16(const TileView& t, int r0, int c0) {
     return x;
 }
 
+template <bool CO>
 __device__ __forceinline__ void store16(const TileView& t, int r0, int c0, d4 x) {
     const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) t.put(r0 + 4 * r + g, c0 + j, x[r]);
+    for (int r = 0; r < 4; ++r) t.put<CO>(r0 + 4 * r + g, c0 + j, x[r]);
 }
 
 // Reads of one V/T record through a buffer descriptor: every load of a
@@ -186,7 +198,7 @@ __device__ __forceinline__ double sum16(double v) {
 // nb/16 blocks T_b^T (16 x 16 column-major) -- the same blocked compact-WY
 // form the update kernels apply.
 // ---------------------------------------------------------------------------
-template <int NB, int KIND>
+template <int NB, int KIND, bool CO>
 __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds) {
     using S = Shape<NB>;
     constexpr int MT = S::MT, LDL = S::LDL;
@@ -322,7 +334,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             TbT[l + 16 * i] = til;       // T(i, l)
         }
         lds_barrier();
-        gTt[256 * b + tid] = ((tid & 15) < (tid >> 4)) ? 0.0 : TbT[tid];
+        gstore<CO>(gTt + 256 * b + tid, ((tid & 15) < (tid >> 4)) ? 0.0 : TbT[tid]);
         // Leaf outputs: explicit U_b tails into the leaf buffer and the record,
         // R (GEQRT) or zeros (TS/TT) into the matrix.
         {
@@ -334,11 +346,11 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 if (PAIR) vv = (TT && row > col) ? 0.0 : x[s];
                 else vv = row > col ? x[s] : (row == col ? 1.0 : 0.0);
                 Lf[row + lj * LDL] = vv;
-                gV[row + (int64_t)col * NB] = vv;
-                gVt[col + (int64_t)row * NB] = vv;
-                TX.put(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
+                gstore<CO>(gV + row + (int64_t)col * NB, vv);
+                gstore<CO>(gVt + col + (int64_t)row * NB, vv);
+                TX.put<CO>(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
             }
-            if (PAIR) T1.put(16 * b + lq, 16 * b + lj, r1);
+            if (PAIR) T1.put<CO>(16 * b + lq, 16 * b + lj, r1);
         }
         lds_barrier();
 
@@ -361,7 +373,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
-                if (PAIR) store16(T1, 16 * b, 16 * J, R1b - W2);
+                if (PAIR) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
 #pragma unroll
                 for (int i = 0; i < MT; ++i) {
                     if (!PAIR && i < b) continue;
@@ -390,7 +402,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 // blocks of V are skipped: V is unit lower triangular after GEQRT and upper
 // triangular after TTQRT.
 // ---------------------------------------------------------------------------
-template <int NB, int KIND>
+template <int NB, int KIND, bool CO>
 __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds) {
     constexpr int MT = NB / 16;
     constexpr int NS = NB >= 64 ? 64 : NB;
@@ -453,7 +465,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
             d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < 4; ++r) W2 = mfma(Ts[j + 16 * (4 * r + g)], W[r], W2);
-            if (HASC1) store16(T1, 16 * b, c0, C1b - W2);
+            if (HASC1) store16<CO>(T1, 16 * b, c0, C1b - W2);
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
                 if (KIND == K_UNMQR && i < b) continue;
@@ -465,19 +477,19 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
         if (b + 1 < MT) stage(b + 1, pre);
         lds_barrier();
     }
-    if (active) store_slice<MT>(T2, c0, c2);
+    if (active) store_slice<CO, MT>(T2, c0, c2);
 }
 
-template <int NB>
+template <int NB, bool CO>
 __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds) {
     const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
     switch (tk.kind) {
-    case K_GEQRT: panel<NB, K_GEQRT>(a, tk, lds); break;
-    case K_TSQRT: panel<NB, K_TSQRT>(a, tk, lds); break;
-    case K_TTQRT: panel<NB, K_TTQRT>(a, tk, lds); break;
-    case K_UNMQR: update<NB, K_UNMQR>(a, tk, part, lds); break;
-    case K_TSMQR: update<NB, K_TSMQR>(a, tk, part, lds); break;
-    default: update<NB, K_TTMQR>(a, tk, part, lds); break;
+    case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds); break;
+    case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds); break;
+    case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds); break;
+    case K_UNMQR: update<NB, K_UNMQR, CO>(a, tk, part, lds); break;
+    case K_TSMQR: update<NB, K_TSMQR, CO>(a, tk, part, lds); break;
+    default: update<NB, K_TTMQR, CO>(a, tk, part, lds); break;
     }
 }
 
@@ -488,7 +500,7 @@ template <int NB>
 __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
     __shared__ double lds[Shape<NB>::LDS];
     const int2 u = a.units[unit_base + blockIdx.x];
-    run_unit<NB>(a, u.x, u.y, lds);
+    run_unit<NB, false>(a, u.x, u.y, lds);
 }
 
 // Persistent scheduler.  Each workgroup repeatedly takes the next ticket (a
@@ -540,9 +552,12 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(s_stop)) break;
+        // Acquire: drop stale lines of the inputs from this CU's caches and
+        // this XCD's L2.  Release: the unit wrote its outputs with agent-scope
+        // stores, so waiting for them to complete publishes them to every XCD.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        run_unit<NB>(a, un.x, un.y, lds);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        run_unit<NB, true>(a, un.x, un.y, lds);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
             const int s0 = a.succ_off[un.x], s1 = a.succ_off[un.x + 1];
