@@ -170,6 +170,26 @@ int bb_poll_error(const void* ws, void* stream, int* device_status);
 int bb_plan_last_kernel_ms(bb_plan* plan, double* ms);
 
 /*
+ * bb_graph_check -- static race check of a task graph in the bb_plan_export
+ * format (host only): predecessors precede their task, every two consecutive
+ * tasks touching the same tile are joined by an edge (tile accesses are
+ * read-modify-write, Algorithms 2 and 3), and each update depends on the
+ * panel that wrote its V/T slot.  Arguments: tile grid p (1) >= q (2) >= 1,
+ * ntasks (3), tasks/pred_off/pred_idx (4-6).  Returns BB_OK or BB_EDAG.
+ * bb_plan_create runs the same check on every graph it builds.
+ */
+int bb_graph_check(int p, int q, int64_t ntasks, const int32_t* tasks, const int32_t* pred_off,
+                   const int32_t* pred_idx);
+
+/*
+ * FlatTS domain size Auto chose for each QR/LQ step of the plan (Section 5:
+ * the largest a with ceil(u/a) * v >= gamma * workgroups for a step with u
+ * panel tiles and v trailing tiles, else 1); 0 for steps of other trees.
+ * Pass a = NULL to query *nsteps only.
+ */
+int bb_plan_auto_domains(const bb_plan* plan, int32_t* a, int64_t* nsteps);
+
+/*
  * Critical path (Section 4) of the task graph for a p x q tile matrix, with
  * the Table 1 weights, host only.  Returns a negative value on bad input.
  */

@@ -52,7 +52,8 @@ _lib = None
 # Every symbol include/bidiag.h declares.
 EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_get_stats",
            "bb_plan_export", "bb_execute", "bidiag_band", "bb_query", "bb_poll_error",
-           "bb_plan_last_kernel_ms", "bb_critical_path", "bb_strerror"]
+           "bb_plan_last_kernel_ms", "bb_critical_path", "bb_strerror", "bb_graph_check",
+           "bb_plan_auto_domains"]
 
 
 def lib():
@@ -92,6 +93,10 @@ def lib():
     L.bb_plan_last_kernel_ms.restype = i32
     L.bb_critical_path.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_double]
     L.bb_critical_path.restype = ctypes.c_double
+    L.bb_graph_check.argtypes = [i32, i32, i64, vp, vp, vp]
+    L.bb_graph_check.restype = i32
+    L.bb_plan_auto_domains.argtypes = [P, vp, ctypes.POINTER(i64)]
+    L.bb_plan_auto_domains.restype = i32
     L.bb_strerror.argtypes = [i32]
     L.bb_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -117,6 +122,17 @@ def critical_path(p: int, q: int, tree="greedy", variant="bidiag", auto_a=0, wor
                   gamma=2.0) -> float:
     """Critical path (Section 4) in units of nb^3/3 with Table 1 weights."""
     return lib().bb_critical_path(p, q, TREES[tree], VARIANTS[variant], auto_a, workgroups, gamma)
+
+
+def graph_check(p, q, tasks, pred_off, pred_idx) -> int:
+    """Static race check of an exported task graph (BB_OK = 0 or BB_EDAG)."""
+    tasks = np.ascontiguousarray(tasks, dtype=np.int32)
+    pred_off = np.ascontiguousarray(pred_off, dtype=np.int32)
+    pred_idx = np.ascontiguousarray(pred_idx, dtype=np.int32)
+    if pred_idx.size == 0:
+        pred_idx = np.zeros(1, dtype=np.int32)
+    return lib().bb_graph_check(int(p), int(q), int(tasks.shape[0]), tasks.ctypes.data,
+                                pred_off.ctypes.data, pred_idx.ctypes.data)
 
 
 def _stream_handle(stream):
@@ -170,6 +186,15 @@ class Plan:
         _check(lib().bb_plan_export(self._h, tasks.ctypes.data, off.ctypes.data, idx.ctypes.data,
                                     ctypes.byref(npred)), "bb_plan_export")
         return tasks, off, idx[:npred.value]
+
+    def auto_domains(self):
+        """Auto's FlatTS domain size per QR/LQ step (0 for other trees)."""
+        ns = ctypes.c_int64()
+        _check(lib().bb_plan_auto_domains(self._h, None, ctypes.byref(ns)), "bb_plan_auto_domains")
+        out = np.zeros(max(1, ns.value), dtype=np.int32)
+        _check(lib().bb_plan_auto_domains(self._h, out.ctypes.data, ctypes.byref(ns)),
+               "bb_plan_auto_domains")
+        return out[:ns.value]
 
     def alloc(self, device=None):
         """Allocate (vt, ws) byte buffers of the sizes this plan needs."""

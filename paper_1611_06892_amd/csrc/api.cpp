@@ -305,6 +305,22 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
             delete P;
             return BB_EDAG;
         }
+        // Static race check of the generated graph before anything runs.
+        {
+            const size_t nt = P->g.tasks.size();
+            std::vector<int32_t> tk(8 * nt), off(nt + 1, 0), idx;
+            for (size_t t = 0; t < nt; ++t) {
+                const bb::Task& x = P->g.tasks[t];
+                int32_t v[8] = {x.kind, x.trans, x.r1, x.c1, x.r2, x.c2, x.slot, x.step};
+                std::copy(v, v + 8, tk.begin() + 8 * t);
+                for (int32_t pr : P->g.pred[t]) idx.push_back(pr);
+                off[t + 1] = (int32_t)idx.size();
+            }
+            if (!bb::check_graph((int)p, (int)q, (int64_t)nt, tk.data(), off.data(), idx.data()).empty()) {
+                delete P;
+                return BB_EDAG;
+            }
+        }
         int rc = build_schedule(*P);
         if (rc != BB_OK) {
             delete P;
@@ -497,6 +513,26 @@ int bb_poll_error(const void* ws, void* stream, int* device_status) {
                   hipMemcpyDeviceToHost) != hipSuccess)
         return BB_EHIP;
     *device_status = e;
+    return BB_OK;
+}
+
+int bb_graph_check(int p, int q, int64_t ntasks, const int32_t* tasks, const int32_t* pred_off,
+                   const int32_t* pred_idx) {
+    if (q < 1 || p < q) return -1;
+    if (ntasks < 0) return -3;
+    if (ntasks > 0 && (!tasks || !pred_off || (!pred_idx && pred_off[ntasks] > 0))) return -4;
+    try {
+        return bb::check_graph(p, q, ntasks, tasks, pred_off, pred_idx).empty() ? BB_OK : BB_EDAG;
+    } catch (...) {
+        return BB_ENOMEM;
+    }
+}
+
+int bb_plan_auto_domains(const bb_plan* P, int32_t* a, int64_t* nsteps) {
+    if (!P) return -1;
+    if (nsteps) *nsteps = (int64_t)P->g.auto_a_used.size();
+    if (a)
+        for (size_t k = 0; k < P->g.auto_a_used.size(); ++k) a[k] = P->g.auto_a_used[k];
     return BB_OK;
 }
 

@@ -217,6 +217,53 @@ std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g) {
     return std::string();
 }
 
+std::string check_graph(int p, int q, int64_t nt, const int32_t* tk, const int32_t* off,
+                        const int32_t* idx) {
+    std::vector<int32_t> last((size_t)p * q, -1), slot_owner;
+    auto has_edge = [&](int64_t t, int32_t pr) {
+        for (int32_t e = off[t]; e < off[t + 1]; ++e)
+            if (idx[e] == pr) return true;
+        return false;
+    };
+    char buf[160];
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* x = tk + 8 * t;
+        for (int32_t e = off[t]; e < off[t + 1]; ++e)
+            if (idx[e] < 0 || idx[e] >= t) {
+                snprintf(buf, sizeof buf, "task %lld: predecessor %d does not precede it", (long long)t, idx[e]);
+                return buf;
+            }
+        const int kind = x[0];
+        if (kind < GEQRT || kind > TTMQR) return "unknown task kind";
+        const int32_t coords[2][2] = {{x[2], x[3]}, {x[4], x[5]}};
+        for (int k = 0; k < 2; ++k) {
+            const int r = coords[k][0], c = coords[k][1];
+            if (r < 0) continue;
+            if (r >= p || c >= q) return "tile out of range";
+            int32_t& l = last[(size_t)r * q + c];
+            if (l >= 0 && !has_edge(t, l)) {
+                snprintf(buf, sizeof buf, "tasks %d and %lld touch tile (%d,%d) without an edge", l, (long long)t, r, c);
+                return buf;
+            }
+            l = (int32_t)t;
+        }
+        const int32_t slot = x[6];
+        if (slot < 0) return "negative slot";
+        if (is_panel(kind)) {
+            if ((size_t)slot >= slot_owner.size()) slot_owner.resize(slot + 1, -1);
+            if (slot_owner[slot] >= 0) return "V/T slot written twice";
+            slot_owner[slot] = (int32_t)t;
+        } else {
+            if ((size_t)slot >= slot_owner.size() || slot_owner[slot] < 0) return "update reads an unwritten slot";
+            if (!has_edge(t, slot_owner[slot])) {
+                snprintf(buf, sizeof buf, "update %lld does not depend on the panel of its slot", (long long)t);
+                return buf;
+            }
+        }
+    }
+    return std::string();
+}
+
 double critical_path(const Graph& g, const double* w) {
     std::vector<double> fin(g.tasks.size(), 0.0);
     double best = 0.0;

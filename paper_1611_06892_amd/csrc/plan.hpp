@@ -68,6 +68,15 @@ std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g);
 // UNMQR 6, TSMQR 12, TTMQR 6.
 extern const double kTable1Weights[6];
 
+// Static race check of a task graph given as arrays (program order):
+// predecessors precede their task; every two consecutive tasks touching the
+// same tile are ordered by an edge (all tile accesses are read-modify-write,
+// so this orders every conflicting pair); every update depends on the panel
+// that wrote its V/T slot, which is written by exactly one panel.  Returns an
+// empty string when the graph is race-free, else a description.
+std::string check_graph(int p, int q, int64_t ntasks, const int32_t* tasks,
+                        const int32_t* pred_off, const int32_t* pred_idx);
+
 // Longest weighted path (critical path, Section 4) with per-kind weights.
 double critical_path(const Graph& g, const double* weights);
 
