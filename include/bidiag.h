@@ -59,8 +59,16 @@ enum { BB_FLATTS = 0, BB_FLATTT = 1, BB_GREEDY = 2, BB_AUTO = 3 };
  * only the tiled QR factorization QR(p,q) of Algorithm 1 (A is overwritten by
  * R, rows >= n zero). */
 enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2 };
-/* Arithmetic: BB_F64 computes everything in FP64. */
-enum { BB_F64 = 0 };
+/* Arithmetic.  BB_F64 computes everything in FP64.  The two other modes keep
+ * the matrix, the panels (reflector generation, V and T) in FP64 and run the
+ * trailing updates (UNMQR/TSMQR/TTMQR and their LQ twins) on FP32 matrix
+ * cores: BB_F64_UPD_F32 rounds the operands to FP32 (RNE), accumulates each
+ * product in FP32 and adds it into the FP64 tiles; BB_F64_UPD_SPLIT32 also
+ * carries the FP32 rounding error of every operand (x = x_hi + x_lo), forms
+ * A_hi B_hi + A_hi B_lo + A_lo B_hi, and accumulates 16-row chunks in FP64.
+ * (Section 3.6 notes the tile codes exist in single and double precision;
+ * the mixed forms are an extension.) */
+enum { BB_F64 = 0, BB_F64_UPD_F32 = 2, BB_F64_UPD_SPLIT32 = 3 };
 /* Execution of the task graph: one persistent launch whose workgroups take
  * tasks in a precomputed priority order and wait on dependency counters
  * (default), or one launch per topological level of the graph. */
@@ -95,7 +103,7 @@ typedef struct {
 /*
  * bb_plan_create -- build the task graph of one reduction (host only, no GPU
  * call).  Arguments: out plan (1), m (2), n (3) with m >= n >= 1, nb (4) in
- * {32, 64, 128}, tree (5) BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64,
+ * {32, 64, 128}, tree (5) BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64*,
  * opts (8, may be NULL for defaults).  The plan is independent of the data and
  * of lda; it can be executed any number of times.
  */

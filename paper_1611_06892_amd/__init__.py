@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbidiag.so")
 
 TREES = {"flatts": 0, "flattt": 1, "greedy": 2, "auto": 3}
 VARIANTS = {"bidiag": 0, "rbidiag": 1, "qronly": 2}
-PRECS = {"f64": 0}
+PRECS = {"f64": 0, "f64_upd_f32": 2, "f64_upd_split32": 3}
 SCHEDS = {"persistent": 0, "levels": 1}
 KINDS = ["GEQRT", "TSQRT", "TTQRT", "UNMQR", "TSMQR", "TTMQR"]
 FLAG_TIMING = 1

@@ -281,7 +281,7 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
     if (nb < 1) return -4;
     if (tree < BB_FLATTS || tree > BB_AUTO) return -5;
     if (variant < BB_BIDIAG || variant > BB_QRONLY) return -6;
-    if (prec != BB_F64) return -7;
+    if (prec != BB_F64 && prec != BB_F64_UPD_F32 && prec != BB_F64_UPD_SPLIT32) return -7;
     if (m < n) return BB_ENOTSUP;
     if (!bbk::nb_supported(nb)) return BB_ENOTSUP;
     bb_opts o = resolved_opts(opts);
@@ -435,12 +435,12 @@ int bb_execute(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void
         a.units = (const int2*)(blob + P->off_ut);
         int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
         if (wg < 1) wg = 1;
-        if (bbk::launch_persistent(P->nb, a, wg, s) != hipSuccess) return BB_EHIP;
+        if (bbk::launch_persistent(P->nb, P->prec, a, wg, s) != hipSuccess) return BB_EHIP;
     } else {
         a.units = (const int2*)(blob + P->off_ul);
         for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
             int32_t b = P->level_off[l], e = P->level_off[l + 1];
-            if (bbk::launch_level(P->nb, a, b, e - b, s) != hipSuccess) return BB_EHIP;
+            if (bbk::launch_level(P->nb, P->prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
         }
     }
     if (timed && hipEventRecord(P->ev1, s) != hipSuccess) return BB_EHIP;

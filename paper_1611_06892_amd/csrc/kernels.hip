@@ -480,27 +480,205 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     if (active) store_slice<CO, MT>(T2, c0, c2);
 }
 
-template <int NB, bool CO>
+// ---------------------------------------------------------------------------
+// Updates on FP32 MFMA (v_mfma_f32_16x16x4f32), for the precision variants:
+// the V/T block operands and the C operands are rounded to FP32 (RNE), each
+// product accumulates in FP32, and its result is added into the FP64 tiles.
+// SPLIT: every operand x is also carried as x_lo = fp32(x - x_hi) and a
+// product A B is taken as A_hi B_hi + A_hi B_lo + A_lo B_hi, accumulated in
+// FP32 over 16-row chunks and in FP64 across chunks.  Panels, V and T stay
+// FP64 in either case.
+//
+// The FP32 instruction returns element r of lane l at row 4(l/16) + r (the
+// FP64 one at row 4r + l/16).  Slices are therefore held in that layout, and
+// the k-step r of a 16-row block takes the rows {4g + r : g = 0..3}: lane l
+// supplies row 4(l/16) + r of its column, which is its own element r.
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int MT>
+__device__ __forceinline__ void load_slice_r4(const TileView& t, int c0, d4 (&x)[MT]) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[i][r] = t.get(16 * i + 4 * g + r, c0 + j);
+}
+
+template <bool CO, int MT>
+__device__ __forceinline__ void store_slice_r4(const TileView& t, int c0, const d4 (&x)[MT]) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t.put<CO>(16 * i + 4 * g + r, c0 + j, x[i][r]);
+}
+
+__device__ __forceinline__ d4 load16_r4(const TileView& t, int r0, int c0) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    d4 x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = t.get(r0 + 4 * g + r, c0 + j);
+    return x;
+}
+
+template <bool CO>
+__device__ __forceinline__ void store16_r4(const TileView& t, int r0, int c0, d4 x) {
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t.put<CO>(r0 + 4 * g + r, c0 + j, x[r]);
+}
+
+__device__ __forceinline__ float lo32(double x, float hi) { return (float)(x - (double)hi); }
+
+template <int NB, int KIND, bool CO, bool SPLIT>
+__device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int part, double* lds) {
+    constexpr int MT = NB / 16;
+    constexpr int NS = NB >= 64 ? 64 : NB;
+    constexpr int LDV = NB + 1;
+    constexpr int PL = 16 * LDV + 256;        // floats per plane: V_b (NB x 16) then T_b^T
+    constexpr int BUF = (SPLIT ? 2 : 1) * PL; // hi plane [, lo plane]
+    constexpr int PRE = NB / 16 + 1;
+    constexpr bool HASC1 = KIND != K_UNMQR;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
+    const int c0 = part * NS + 16 * w;
+    const TileView T2 = view(a, tk.r2, tk.c2, tk.trans, NB);
+    const TileView T1 = HASC1 ? view(a, tk.r1, tk.c1, tk.trans, NB) : T2;
+    const bool active = 16 * w < NS && c0 < T2.vc;
+    const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
+    float* fl = reinterpret_cast<float*>(lds);
+
+    auto fetch = [&](int b, double (&pre)[PRE]) {
+#pragma unroll
+        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
+        pre[PRE - 1] = rec.ld(8 * tid, 8 * (2 * NB * NB + 256 * b));
+    };
+    auto stage = [&](int b, const double (&pre)[PRE]) {
+        float* hi = fl + (b & 1) * BUF;
+        float* lo = hi + PL;
+#pragma unroll
+        for (int k = 0; k < PRE - 1; ++k) {
+            const int e = tid + 256 * k;
+            const int at = (e % NB) + (e / NB) * LDV;
+            const float h = (float)pre[k];
+            hi[at] = h;
+            if (SPLIT) lo[at] = lo32(pre[k], h);
+        }
+        const float h = (float)pre[PRE - 1];
+        hi[16 * LDV + tid] = h;
+        if (SPLIT) lo[16 * LDV + tid] = lo32(pre[PRE - 1], h);
+    };
+    // Product of a (16 x 4) A-fragment pair with a B-fragment given in FP64.
+    auto prod = [&](float ah, float al, double bv, f4 acc) {
+        const float bh = (float)bv;
+        acc = mfma32(ah, bh, acc);
+        if (SPLIT) {
+            acc = mfma32(ah, lo32(bv, bh), acc);
+            acc = mfma32(al, bh, acc);
+        }
+        return acc;
+    };
+
+    d4 c2[MT];
+    if (active) load_slice_r4<MT>(T2, c0, c2);
+    double pre[PRE];
+    fetch(0, pre);
+    stage(0, pre);
+    d4 C1n = {0.0, 0.0, 0.0, 0.0};
+    if (HASC1 && active) C1n = load16_r4(T1, 0, c0);
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < MT; ++b) {
+        const float* Vh = fl + (b & 1) * BUF;
+        const float* Vl = Vh + PL;
+        const float* Th = Vh + 16 * LDV;
+        const float* Tl = Vl + 16 * LDV;
+        if (b + 1 < MT) fetch(b + 1, pre);
+        const d4 C1b = C1n;
+        if (HASC1 && active && b + 1 < MT) C1n = load16_r4(T1, 16 * (b + 1), c0);
+        if (active) {
+            // W = C1_b + V_b^T C2, FP64 across 16-row chunks.
+            d4 W = C1b;
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+                f4 ch = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int at = (16 * i + 4 * g + r) + j * LDV;
+                    ch = prod(Vh[at], SPLIT ? Vl[at] : 0.f, c2[i][r], ch);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W[r] += (double)ch[r];
+            }
+            // W2 = T_b^T W
+            f4 w2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int at = j + 16 * (4 * g + r);
+                w2 = prod(Th[at], SPLIT ? Tl[at] : 0.f, W[r], w2);
+            }
+            d4 W2;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) W2[r] = (double)w2[r];
+            if (HASC1) store16_r4<CO>(T1, 16 * b, c0, C1b - W2);
+            // C2 -= V_b W2
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+                f4 ch = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int at = (16 * i + j) + (4 * g + r) * LDV;
+                    ch = prod(-Vh[at], SPLIT ? -Vl[at] : 0.f, W2[r], ch);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c2[i][r] += (double)ch[r];
+            }
+        }
+        if (b + 1 < MT) stage(b + 1, pre);
+        lds_barrier();
+    }
+    if (active) store_slice_r4<CO, MT>(T2, c0, c2);
+}
+
+// PREC: 0 = FP64 updates, 2 = FP32-MFMA updates, 3 = split-FP32 updates.
+template <int NB, bool CO, int PREC>
 __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds) {
     const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
     switch (tk.kind) {
     case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds); break;
     case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds); break;
     case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds); break;
-    case K_UNMQR: update<NB, K_UNMQR, CO>(a, tk, part, lds); break;
-    case K_TSMQR: update<NB, K_TSMQR, CO>(a, tk, part, lds); break;
-    default: update<NB, K_TTMQR, CO>(a, tk, part, lds); break;
+    case K_UNMQR:
+        if (PREC == 0) update<NB, K_UNMQR, CO>(a, tk, part, lds);
+        else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds);
+        break;
+    case K_TSMQR:
+        if (PREC == 0) update<NB, K_TSMQR, CO>(a, tk, part, lds);
+        else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds);
+        break;
+    default:
+        if (PREC == 0) update<NB, K_TTMQR, CO>(a, tk, part, lds);
+        else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds);
+        break;
     }
 }
 
 }  // namespace
 
 // One launch per topological level: block b runs unit unit_base + b.
-template <int NB>
+template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
     __shared__ double lds[Shape<NB>::LDS];
     const int2 u = a.units[unit_base + blockIdx.x];
-    run_unit<NB, false>(a, u.x, u.y, lds);
+    run_unit<NB, false, PREC>(a, u.x, u.y, lds);
 }
 
 // Persistent scheduler.  Each workgroup repeatedly takes the next ticket (a
@@ -511,7 +689,7 @@ __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
 // lowest unfinished ticket can always proceed: no deadlock for any grid size.
 // A wall-clock watchdog bounds every wait; on expiry (or when another
 // workgroup reports an error) the workgroup records the error and exits.
-template <int NB>
+template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
     __shared__ double lds[Shape<NB>::LDS];
     __shared__ int s_unit, s_stop;
@@ -556,7 +734,7 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
         // this XCD's L2.  Release: the unit wrote its outputs with agent-scope
         // stores, so waiting for them to complete publishes them to every XCD.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        run_unit<NB, true>(a, un.x, un.y, lds);
+        run_unit<NB, true, PREC>(a, un.x, un.y, lds);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
@@ -585,24 +763,28 @@ hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks
 
 bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128; }
 
-hipError_t launch_level(int nb, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    switch (nb) {
-    case 32: hipLaunchKernelGGL(level_kernel<32>, dim3(count), dim3(NT), 0, s, a, unit_base); break;
-    case 64: hipLaunchKernelGGL(level_kernel<64>, dim3(count), dim3(NT), 0, s, a, unit_base); break;
-    case 128: hipLaunchKernelGGL(level_kernel<128>, dim3(count), dim3(NT), 0, s, a, unit_base); break;
-    default: return hipErrorInvalidValue;
+#define BB_DISPATCH(KERNEL, GRID, ...)                                                   \
+    switch (nb * 4 + prec) {                                                             \
+    case 32 * 4 + 0: hipLaunchKernelGGL((KERNEL<32, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 32 * 4 + 2: hipLaunchKernelGGL((KERNEL<32, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 32 * 4 + 3: hipLaunchKernelGGL((KERNEL<32, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 64 * 4 + 0: hipLaunchKernelGGL((KERNEL<64, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 64 * 4 + 2: hipLaunchKernelGGL((KERNEL<64, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 64 * 4 + 3: hipLaunchKernelGGL((KERNEL<64, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
+    case 128 * 4 + 0: hipLaunchKernelGGL((KERNEL<128, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
+    case 128 * 4 + 2: hipLaunchKernelGGL((KERNEL<128, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
+    case 128 * 4 + 3: hipLaunchKernelGGL((KERNEL<128, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                \
     }
+
+hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    BB_DISPATCH(level_kernel, dim3(count), a, unit_base)
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(int nb, const KArgs& a, int32_t workgroups, hipStream_t s) {
-    switch (nb) {
-    case 32: hipLaunchKernelGGL(persistent_kernel<32>, dim3(workgroups), dim3(NT), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(persistent_kernel<64>, dim3(workgroups), dim3(NT), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(persistent_kernel<128>, dim3(workgroups), dim3(NT), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
+hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s) {
+    BB_DISPATCH(persistent_kernel, dim3(workgroups), a)
     return hipGetLastError();
 }
 

@@ -37,8 +37,9 @@ inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
-hipError_t launch_level(int nb, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
-hipError_t launch_persistent(int nb, const KArgs& a, int32_t workgroups, hipStream_t s);
+// prec: 0 = FP64, 2 = FP32-MFMA updates, 3 = split-FP32 updates (bidiag.h's BB_F64*).
+hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
+hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s);
 bool nb_supported(int nb);
 
 }  // namespace bbk

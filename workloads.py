@@ -61,6 +61,22 @@ def graded(m: int, n: int, seed_u: int, seed_v: int, smin: float):
     return A, s
 
 
+def graded_device(m: int, n: int, seed_u: int, seed_v: int, smin: float, device="cuda"):
+    """Same recipe as graded() for sizes where a host QR is too slow: the
+    Gaussians come from a seeded torch generator on `device` and the Q factors
+    from torch.linalg.qr there.  Returns (A as an m x n torch tensor, s)."""
+    import torch
+    s = geometric_sigmas(n, smin)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed_u)
+    U, _ = torch.linalg.qr(torch.randn(m, n, generator=gen, device=device, dtype=torch.float64))
+    gen.manual_seed(seed_v)
+    V, _ = torch.linalg.qr(torch.randn(n, n, generator=gen, device=device, dtype=torch.float64))
+    st = torch.from_numpy(s).to(device)
+    A = (U * st[None, :]) @ V.t().contiguous()
+    return A, s
+
+
 def batch_shapes(count: int, seed: int, mlo: int = 64, mhi: int = 1024, nlo: int = 32):
     """Draw (m, n) pairs, then the entries, from one generator.  Returns a list
     of column-major FP64 matrices."""
