@@ -40,7 +40,8 @@ def test_argument_errors():
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 48, 0, 0, 0, ctypes.byref(opts)) == 1   # nb
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 9, 0, 0, ctypes.byref(opts)) == -5  # tree
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 0, 7, 0, ctypes.byref(opts)) == -6  # variant
-    assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 0, 0, 3, ctypes.byref(opts)) == -7  # prec
+    assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 0, 0, 1, ctypes.byref(opts)) == -7  # prec
+    assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 0, 0, 4, ctypes.byref(opts)) == -7
     assert L.bb_plan_create(ctypes.byref(h), 0, 0, 64, 0, 0, 0, ctypes.byref(opts)) == -2
     assert L.bb_plan_create(None, 100, 50, 64, 0, 0, 0, ctypes.byref(opts)) == -1
     p = bb.Plan(300, 200, 64, "greedy", "bidiag")
