@@ -164,6 +164,109 @@ int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, cons
              size_t* vt_bytes, size_t* ws_bytes);
 
 /*
+ * bb_apply_q / bb_apply_p -- apply the orthogonal factors of a finished
+ * reduction, read from its V/T records (Sections 3.4 and 3.5: B = Q^T A P,
+ * Q the product of the QR-step panel reflectors in task order, P that of the
+ * LQ-step ones, so A = Q B P^T).
+ *   bb_apply_q: C (m x ncols) <- Q C       (transpose = 0) or Q^T C (1);
+ *   bb_apply_p: C (n x ncols) <- P C       (transpose = 0) or P^T C (1).
+ * (C P is (P^T C^T)^T.)  Arguments: plan (1) of the reduction that wrote vt;
+ * transpose (2); vt (3) with vt_bytes (4) as from bb_plan_workspace, device,
+ * read only; C (5) device, column-major, ldc (6) >= rows of C, modified in
+ * place; ncols (7) >= 0 (0: nothing is done); ws (8) with ws_bytes (9) >=
+ * bb_apply_workspace's size (scheduler state, contents not kept); stream
+ * (10).  Runs on FP64 matrix cores whatever the plan's prec.  The plan keeps
+ * one host/device task graph per (side, transpose, ceil(ncols/nb)); a plan
+ * must not be used from several host threads at once for these calls.
+ */
+int bb_apply_q(bb_plan* plan, int transpose, const void* vt, size_t vt_bytes, void* C,
+               int64_t ldc, int64_t ncols, void* ws, size_t ws_bytes, void* stream);
+int bb_apply_p(bb_plan* plan, int transpose, const void* vt, size_t vt_bytes, void* C,
+               int64_t ldc, int64_t ncols, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for bb_apply_q (side 0) or bb_apply_p (side 1) with the
+ * given transpose and column count (host only). */
+int bb_apply_workspace(bb_plan* plan, int side, int transpose, int64_t ncols, size_t* ws_bytes);
+
+/* ---- batches of independent reductions ------------------------------- */
+/*
+ * A batch reduces `count` independent matrices, each by its own task graph
+ * (the graphs of Sections 3.4/3.5 for its own p x q tile grid, nb, tree and
+ * variant).  The graphs of all matrices with the same nb are joined, without
+ * edges between matrices, into one graph that one persistent launch
+ * executes; the (at most three) tile sizes run one after the other on the
+ * stream.  Sizes may differ freely (ragged tiles as in the single form).
+ */
+typedef struct bb_batch bb_batch;
+
+/*
+ * bb_tuned_config -- the (nb, tree, variant) that the offline tuner measured
+ * as fastest (batch throughput) for the size class of an m x n matrix.
+ * Arguments: m (1) >= n (2) >= 1, prec (3), out nb/tree/variant (4-6).
+ */
+int bb_tuned_config(int64_t m, int64_t n, int prec, int* nb, int* tree, int* variant);
+
+/*
+ * bb_batch_create -- plan a batch (host only).  Arguments: out batch (1);
+ * count (2) >= 0; m (3), n (4): host arrays of count sizes, m[i] >= n[i] >= 1;
+ * nb (5), tree (6), variant (7): host arrays or NULL.  nb == NULL or
+ * nb[i] == 0 selects bb_tuned_config's choice for matrix i (tree and variant
+ * entries are then ignored); otherwise tree == NULL means BB_GREEDY and
+ * variant == NULL BB_BIDIAG.  prec (8), opts (9) as in bb_plan_create.
+ */
+int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int64_t* n,
+                    const int* nb, const int* tree, const int* variant, int prec,
+                    const bb_opts* opts);
+void bb_batch_destroy(bb_batch* batch);
+
+/* Device bytes for the records of all matrices and the scheduler state. */
+int bb_batch_workspace(const bb_batch* batch, size_t* vt_bytes, size_t* ws_bytes);
+
+/*
+ * Per-matrix facts of a batch: the nb/tree/variant used, the byte offset of
+ * matrix i's first V/T record in vt and its number of records (records of one
+ * matrix are contiguous, in the order of its task graph, in the format of
+ * bb_plan_workspace for that nb).
+ */
+int bb_batch_info(const bb_batch* batch, int64_t i, int* nb, int* tree, int* variant,
+                  int64_t* rec_offset, int64_t* nrec);
+
+/*
+ * bb_batch_execute -- reduce every matrix of the batch in place.  A (2):
+ * DEVICE array of count device pointers (matrix i column-major, m[i] x n[i]);
+ * lda (3): DEVICE array of count leading dimensions, lda[i] >= m[i] (read by
+ * the device, not validated on the host); vt (4)/vt_bytes (5), ws (6)/
+ * ws_bytes (7) >= bb_batch_workspace's sizes; stream (8).  Device-side errors
+ * are read with bb_batch_poll_error.
+ */
+int bb_batch_execute(bb_batch* batch, double* const* A, const int64_t* lda, void* vt,
+                     size_t vt_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Milliseconds between HIP events recorded before the first and after the
+ * last launch of the last bb_batch_execute (requires BB_FLAG_TIMING). */
+int bb_batch_last_kernel_ms(bb_batch* batch, double* ms);
+
+/* bb_poll_error over every launch of a batch's last execution. */
+int bb_batch_poll_error(const bb_batch* batch, const void* ws, void* stream, int* device_status);
+
+/* Workspace sizes of a batch (arguments as bb_batch_create from count on). */
+int bb_query_batched(int64_t count, const int64_t* m, const int64_t* n, const int* nb,
+                     const int* tree, const int* variant, int prec, const bb_opts* opts,
+                     size_t* vt_bytes, size_t* ws_bytes);
+
+/*
+ * bidiag_band_batched -- one-shot bb_batch_create + bb_batch_execute with the
+ * batch plan cached inside the library by its arguments.  Numbering: A (1),
+ * lda (2) (device arrays), count (3), m (4), n (5), nb (6), tree (7),
+ * variant (8) (host arrays), prec (9), vt (10), vt_bytes (11), ws (12),
+ * ws_bytes (13), opts (14), stream (15).
+ */
+int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, const int64_t* m,
+                        const int64_t* n, const int* nb, const int* tree, const int* variant,
+                        int prec, void* vt, size_t vt_bytes, void* ws, size_t ws_bytes,
+                        const bb_opts* opts, void* stream);
+
+/*
  * bb_poll_error -- synchronize `stream` and read the scheduler's error word
  * from ws: *device_status = 0 if the last execution completed, else a BB_E*
  * code.  Returns BB_OK or BB_EHIP.

@@ -167,13 +167,11 @@ def band_violation(B: np.ndarray, nb: int) -> float:
     return float(np.max(np.abs(B[outside]))) if B.size else 0.0
 
 
-def sign_normalize(B: np.ndarray, nb: int) -> np.ndarray:
-    """Representative of {D1 B D2} with B(i,i) >= 0 and B(i,i+nb) >= 0.
-
-    t_c = +1 for c < nb; for i = 0..n-1: s_i = sgn(B_ii t_i), then
-    t_{i+nb} = sgn(B_{i,i+nb} s_i) when i + nb < n (sgn(0) = +1).
-    Returns diag(s) B[:n, :] diag(t) (the n x n leading block).
-    """
+def sign_vectors(B: np.ndarray, nb: int):
+    """The +-1 vectors (s, t) of sign_normalize: t_c = +1 for c < nb; for
+    i = 0..n-1: s_i = sgn(B_ii t_i), then t_{i+nb} = sgn(B_{i,i+nb} s_i) when
+    i + nb < n (sgn(0) = +1).  With A = Q B P^T, also A = (Q diag(s))
+    (diag(s) B diag(t)) (P diag(t))^T."""
     B = np.asarray(B, dtype=np.float64)
     n = B.shape[1]
     s = np.ones(n)
@@ -182,6 +180,16 @@ def sign_normalize(B: np.ndarray, nb: int) -> np.ndarray:
         s[i] = 1.0 if B[i, i] * t[i] >= 0 else -1.0
         if i + nb < n:
             t[i + nb] = 1.0 if B[i, i + nb] * s[i] >= 0 else -1.0
+    return s, t
+
+
+def sign_normalize(B: np.ndarray, nb: int) -> np.ndarray:
+    """Representative of {D1 B D2} with B(i,i) >= 0 and B(i,i+nb) >= 0:
+    diag(s) B[:n, :] diag(t) with (s, t) from sign_vectors (the n x n leading
+    block)."""
+    B = np.asarray(B, dtype=np.float64)
+    n = B.shape[1]
+    s, t = sign_vectors(B, nb)
     return (s[:, None] * B[:n, :]) * t[None, :]
 
 

@@ -53,7 +53,10 @@ _lib = None
 EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_get_stats",
            "bb_plan_export", "bb_execute", "bidiag_band", "bb_query", "bb_poll_error",
            "bb_plan_last_kernel_ms", "bb_critical_path", "bb_strerror", "bb_graph_check",
-           "bb_plan_auto_domains"]
+           "bb_plan_auto_domains", "bb_apply_q", "bb_apply_p", "bb_apply_workspace",
+           "bb_tuned_config", "bb_batch_create", "bb_batch_destroy", "bb_batch_workspace",
+           "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
+           "bb_query_batched", "bidiag_band_batched"]
 
 
 def lib():
@@ -97,6 +100,36 @@ def lib():
     L.bb_graph_check.restype = i32
     L.bb_plan_auto_domains.argtypes = [P, vp, ctypes.POINTER(i64)]
     L.bb_plan_auto_domains.restype = i32
+    for name in ("bb_apply_q", "bb_apply_p"):
+        f = getattr(L, name)
+        f.argtypes = [P, i32, vp, ctypes.c_size_t, vp, i64, i64, vp, ctypes.c_size_t, vp]
+        f.restype = i32
+    L.bb_apply_workspace.argtypes = [P, i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.bb_apply_workspace.restype = i32
+    ip, lp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    L.bb_tuned_config.argtypes = [i64, i64, i32, ip, ip, ip]
+    L.bb_tuned_config.restype = i32
+    L.bb_batch_create.argtypes = [ctypes.POINTER(P), i64, vp, vp, vp, vp, vp, i32,
+                                  ctypes.POINTER(_Opts)]
+    L.bb_batch_create.restype = i32
+    L.bb_batch_destroy.argtypes = [P]
+    L.bb_batch_destroy.restype = None
+    L.bb_batch_workspace.argtypes = [P, szp, szp]
+    L.bb_batch_workspace.restype = i32
+    L.bb_batch_info.argtypes = [P, i64, ip, ip, ip, lp, lp]
+    L.bb_batch_info.restype = i32
+    L.bb_batch_execute.argtypes = [P, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp]
+    L.bb_batch_execute.restype = i32
+    L.bb_batch_last_kernel_ms.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    L.bb_batch_last_kernel_ms.restype = i32
+    L.bb_batch_poll_error.argtypes = [P, vp, vp, ip]
+    L.bb_batch_poll_error.restype = i32
+    L.bb_query_batched.argtypes = [i64, vp, vp, vp, vp, vp, i32, ctypes.POINTER(_Opts), szp, szp]
+    L.bb_query_batched.restype = i32
+    L.bidiag_band_batched.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp, ctypes.c_size_t,
+                                      vp, ctypes.c_size_t, ctypes.POINTER(_Opts), vp]
+    L.bidiag_band_batched.restype = i32
     L.bb_strerror.argtypes = [i32]
     L.bb_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -213,6 +246,32 @@ class Plan:
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                 _stream_handle(stream)), "bb_execute")
 
+    def apply_workspace(self, side, transpose, ncols) -> int:
+        ws = ctypes.c_size_t()
+        _check(lib().bb_apply_workspace(self._h, int(side), int(transpose), int(ncols),
+                                        ctypes.byref(ws)), "bb_apply_workspace")
+        return ws.value
+
+    def _apply(self, side, Ccm, ldc, ncols, vt, transpose, ws, stream):
+        import torch
+        if ws is None:
+            ws = torch.empty(max(self.apply_workspace(side, transpose, ncols), 8),
+                             dtype=torch.uint8, device=Ccm.device)
+        fn = lib().bb_apply_q if side == 0 else lib().bb_apply_p
+        _check(fn(self._h, int(bool(transpose)), ctypes.c_void_p(vt.data_ptr()),
+                  vt.numel() * vt.element_size(), ctypes.c_void_p(Ccm.data_ptr()), int(ldc),
+                  int(ncols), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                  _stream_handle(stream)), "bb_apply_q" if side == 0 else "bb_apply_p")
+        return ws
+
+    def apply_q(self, Ccm, ldc, ncols, vt, transpose=False, ws=None, stream=None):
+        """C <- Q C (or Q^T C) in place; C is m x ncols column-major at Ccm."""
+        return self._apply(0, Ccm, ldc, ncols, vt, transpose, ws, stream)
+
+    def apply_p(self, Ccm, ldc, ncols, vt, transpose=False, ws=None, stream=None):
+        """C <- P C (or P^T C) in place; C is n x ncols column-major at Ccm."""
+        return self._apply(1, Ccm, ldc, ncols, vt, transpose, ws, stream)
+
     def last_kernel_ms(self) -> float:
         ms = ctypes.c_double()
         _check(lib().bb_plan_last_kernel_ms(self._h, ctypes.byref(ms)), "bb_plan_last_kernel_ms")
@@ -248,3 +307,120 @@ def band(A, nb, tree="auto", variant="bidiag", plan=None, check=True, **opts):
         if st != 0:
             raise BidiagError(st, "device scheduler")
     return S.t(), vt, plan
+
+
+TREE_NAMES = {v: k for k, v in TREES.items()}
+VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
+
+
+def tuned_config(m, n, prec="f64"):
+    """(nb, tree, variant) the offline tuner chose for the size class of m x n."""
+    nb, tr, var = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bb_tuned_config(int(m), int(n), PRECS[prec], ctypes.byref(nb), ctypes.byref(tr),
+                                 ctypes.byref(var)), "bb_tuned_config")
+    return nb.value, TREE_NAMES[tr.value], VARIANT_NAMES[var.value]
+
+
+def _per_matrix(x, count, table, dtype=np.int32):
+    if x is None:
+        return None
+    if isinstance(x, (str, int, np.integer)):
+        x = [x] * count
+    return np.ascontiguousarray([table[v] if table else int(v) for v in x], dtype=dtype)
+
+
+class BatchPlan:
+    """Task graphs of a batch of independent reductions (bb_batch_*)."""
+
+    def __init__(self, shapes, nb=None, tree=None, variant=None, prec="f64", **opts):
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        count = len(self.shapes)
+        self.m = np.ascontiguousarray([s[0] for s in self.shapes], dtype=np.int64)
+        self.n = np.ascontiguousarray([s[1] for s in self.shapes], dtype=np.int64)
+        self._nb = _per_matrix(nb, count, None)
+        self._tree = _per_matrix(tree, count, TREES)
+        self._var = _per_matrix(variant, count, VARIANTS)
+        self.prec = prec
+        self._opts = make_opts(**opts)
+        ptr = lambda a: None if a is None else a.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib().bb_batch_create(ctypes.byref(h), count, ptr(self.m), ptr(self.n), ptr(self._nb),
+                                     ptr(self._tree), ptr(self._var), PRECS[prec],
+                                     ctypes.byref(self._opts)), "bb_batch_create")
+        self._h = h
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bb_batch_destroy(h)
+            self._h = None
+
+    def workspace(self):
+        vt, ws = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().bb_batch_workspace(self._h, ctypes.byref(vt), ctypes.byref(ws)),
+               "bb_batch_workspace")
+        return vt.value, ws.value
+
+    def info(self, i) -> dict:
+        nb, tr, var = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        off, nrec = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().bb_batch_info(self._h, int(i), ctypes.byref(nb), ctypes.byref(tr),
+                                   ctypes.byref(var), ctypes.byref(off), ctypes.byref(nrec)),
+               "bb_batch_info")
+        return {"nb": nb.value, "tree": TREE_NAMES[tr.value], "variant": VARIANT_NAMES[var.value],
+                "rec_offset": off.value, "nrec": nrec.value}
+
+    def alloc(self, device=None):
+        import torch
+        vt_b, ws_b = self.workspace()
+        dev = device if device is not None else torch.device("cuda")
+        return (torch.empty(max(vt_b, 8), dtype=torch.uint8, device=dev),
+                torch.empty(max(ws_b, 8), dtype=torch.uint8, device=dev))
+
+    def execute(self, ptrs, ldas, vt, ws, stream=None):
+        """ptrs, ldas: int64 CUDA tensors (device pointers and leading dimensions)."""
+        _check(lib().bb_batch_execute(self._h, ctypes.c_void_p(ptrs.data_ptr()),
+                                      ctypes.c_void_p(ldas.data_ptr()),
+                                      ctypes.c_void_p(vt.data_ptr()), vt.numel(),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_handle(stream)), "bb_batch_execute")
+
+    def poll_error(self, ws, stream=None) -> int:
+        st = ctypes.c_int()
+        _check(lib().bb_batch_poll_error(self._h, ctypes.c_void_p(ws.data_ptr()),
+                                         _stream_handle(stream), ctypes.byref(st)),
+               "bb_batch_poll_error")
+        return st.value
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(lib().bb_batch_last_kernel_ms(self._h, ctypes.byref(ms)), "bb_batch_last_kernel_ms")
+        return ms.value
+
+
+def pack_batch(mats, device="cuda"):
+    """Copy matrices (numpy or torch, m_i x n_i) column-major into one device
+    buffer.  Returns (buf, ptrs, ldas, offsets): ptrs/ldas are int64 device
+    tensors for BatchPlan.execute, offsets the element offset of each matrix
+    (lda = m)."""
+    import torch
+    sizes = [int(A.shape[0]) * int(A.shape[1]) for A in mats]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    buf = torch.empty(int(offsets[-1]) + 1, dtype=torch.float64, device=device)
+    for A, o, sz in zip(mats, offsets, sizes):
+        T = torch.as_tensor(A, dtype=torch.float64)
+        buf[int(o):int(o) + sz].copy_(T.t().reshape(-1))
+    base = buf.data_ptr()
+    ptrs = torch.as_tensor(base + 8 * offsets[:-1], dtype=torch.int64).to(device)
+    ldas = torch.as_tensor([int(A.shape[0]) for A in mats], dtype=torch.int64).to(device)
+    return buf, ptrs, ldas, offsets
+
+
+def unpack(buf, offsets, shapes, i):
+    """Matrix i of a packed batch as an m x n view (column-major storage)."""
+    m, n = shapes[i]
+    o = int(offsets[i])
+    return buf[o:o + m * n].view(n, m).t()

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -23,6 +24,8 @@
 
 struct bb_plan {
     int64_t m = 0, n = 0;
+    int32_t nmats = 1;                       // matrices of the graph (batched plans)
+    std::vector<int64_t> gidx, dims;         // batched: batch index and (m, n) per matrix
     int nb = 0, tree = 0, variant = 0, prec = 0;
     bb_opts opts{};
     bb::Graph g;
@@ -36,22 +39,51 @@ struct bb_plan {
     int device = -1;
     void* dblob = nullptr;
     size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_ut = 0, off_ul = 0;
+    size_t off_gidx = 0, off_dims = 0;
     int cu_count = 0;
     double wallclock_khz = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
+    // Plans that apply Q, Q^T, P or P^T with this plan's records, by
+    // (side, transpose, tile columns of C).
+    std::map<std::tuple<int, int, int64_t>, bb_plan*> apply;
+    std::mutex apply_mu;
+};
+
+// A batch: one plan (union graph) per tile size, run one after the other.
+struct bb_batch {
+    int64_t count = 0;
+    int prec = 0;
+    bb_opts opts{};
+    std::vector<int64_t> m, n;
+    std::vector<int32_t> nb, tree, variant;
+    struct Group {
+        int nb = 0;
+        bb_plan* plan = nullptr;
+        size_t vt_off = 0, ws_off = 0;   // byte offsets of the group's records / workspace
+    };
+    std::vector<Group> groups;
+    std::vector<int64_t> rec_off;        // per matrix: byte offset of its first record in vt
+    std::vector<int64_t> nrec;           // per matrix: number of records
+    size_t vt_bytes = 0, ws_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    ~bb_batch();
 };
 
 namespace {
 
-const double kUnit[6] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0};   // Table 1
+#include "tuned_table.inc"
+
+// Table 1, then the same update weights for the Q-applying kinds.
+const double kUnit[bb::NKINDS] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0, 6.0, 12.0, 6.0};
 
 // Execution-cost model used to order work on the GPU (relative latency of one
 // task with its column strips run side by side).  Unlike Table 1, whose unit
 // is flops, it reflects that a panel is a chain of nb dependent Householder
 // steps while an update is throughput-bound MFMA work (measured on MI355X for
 // nb = 128: panels ~110 us, UNMQR / TSMQR / TTMQR strips ~25 / 36 / 30 us).
-const double kGpuCost[6] = {11.0, 11.0, 11.0, 2.5, 3.6, 3.0};
+const double kGpuCost[bb::NKINDS] = {11.0, 11.0, 11.0, 2.5, 3.6, 3.0, 2.5, 3.6, 3.0};
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -180,9 +212,14 @@ int build_schedule(bb_plan& P) {
     return validate(P) ? BB_OK : BB_EDAG;
 }
 
+// Workspace: control words, the launch's matrix descriptors, then one
+// dependency counter per task.
+size_t ws_mats_off() { return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256); }
+size_t ws_deps_off(const bb_plan& P) {
+    return ws_mats_off() + round_up(sizeof(bbk::MatDesc) * (size_t)P.nmats, 256);
+}
 size_t ws_bytes_of(const bb_plan& P) {
-    return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256) +
-           round_up(sizeof(int32_t) * P.g.tasks.size(), 256);
+    return ws_deps_off(P) + round_up(sizeof(int32_t) * P.g.tasks.size(), 256);
 }
 
 size_t vt_bytes_of(const bb_plan& P) {
@@ -210,7 +247,7 @@ int ensure_device(bb_plan& P) {
     std::vector<bbk::DevTask> dt(nt);
     for (size_t t = 0; t < nt; ++t) {
         const bb::Task& s = P.g.tasks[t];
-        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, P.nparts[t]};
+        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
     }
     size_t off = 0;
     P.off_tasks = off; off = round_up(off + nt * sizeof(bbk::DevTask), 256);
@@ -219,6 +256,8 @@ int ensure_device(bb_plan& P) {
     P.off_succ_idx = off; off = round_up(off + std::max<size_t>(1, P.succ_idx.size()) * 4, 256);
     P.off_ut = off; off = round_up(off + P.units_ticket.size() * 4, 256);
     P.off_ul = off; off = round_up(off + P.units_level.size() * 4, 256);
+    P.off_gidx = off; off = round_up(off + P.gidx.size() * 8, 256);
+    P.off_dims = off; off = round_up(off + P.dims.size() * 8, 256);
     std::vector<char> host(off, 0);
     std::memcpy(host.data() + P.off_tasks, dt.data(), nt * sizeof(bbk::DevTask));
     std::memcpy(host.data() + P.off_ndeps, P.ndeps.data(), nt * 4);
@@ -226,6 +265,8 @@ int ensure_device(bb_plan& P) {
     if (!P.succ_idx.empty()) std::memcpy(host.data() + P.off_succ_idx, P.succ_idx.data(), P.succ_idx.size() * 4);
     std::memcpy(host.data() + P.off_ut, P.units_ticket.data(), P.units_ticket.size() * 4);
     std::memcpy(host.data() + P.off_ul, P.units_level.data(), P.units_level.size() * 4);
+    if (!P.gidx.empty()) std::memcpy(host.data() + P.off_gidx, P.gidx.data(), P.gidx.size() * 8);
+    if (!P.dims.empty()) std::memcpy(host.data() + P.off_dims, P.dims.data(), P.dims.size() * 8);
     void* d = nullptr;
     if (hipMalloc(&d, off) != hipSuccess) return BB_ENOMEM;
     if (hipMemcpy(d, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
@@ -234,6 +275,92 @@ int ensure_device(bb_plan& P) {
     }
     P.dblob = d;
     P.device = dev;
+    return BB_OK;
+}
+
+// Enqueue one run of plan P on matrix A (arguments already validated).
+// Enqueue one run of plan P (arguments already validated).  d0: the only
+// matrix of a single-matrix plan; NULL when the descriptors of a batched plan
+// are already in the workspace.
+int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* stream) {
+    bb_plan* P = &Pr;
+    int rc = ensure_device(*P);
+    if (rc != BB_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+
+    bbk::KArgs a{};
+    a.mats = (const bbk::MatDesc*)((char*)ws + ws_mats_off());
+    a.vt = (double*)vt;
+    a.slot_stride = bbk::record_doubles(P->nb);
+    char* blob = (char*)P->dblob;
+    a.tasks = (const bbk::DevTask*)(blob + P->off_tasks);
+    a.nunits = (int32_t)(P->units_ticket.size() / 2);
+    a.succ_off = (const int32_t*)(blob + P->off_succ_off);
+    a.succ_idx = (const int32_t*)(blob + P->off_succ_idx);
+    a.ctrl = (int32_t*)ws;
+    a.deps = (int32_t*)((char*)ws + ws_deps_off(*P));
+    a.watchdog_ticks = (int64_t)(P->opts.watchdog_s * P->wallclock_khz * 1000.0);
+
+    const bool timed = (P->opts.flags & BB_FLAG_TIMING) != 0;
+    if (timed && !P->ev0) {
+        if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
+    }
+    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), d0, s) !=
+        hipSuccess)
+        return BB_EHIP;
+    if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
+    if (a.nunits > 0) {
+        if (P->opts.sched == BB_SCHED_PERSISTENT) {
+            a.units = (const int2*)(blob + P->off_ut);
+            int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
+            wg = std::max(1, std::min(wg, a.nunits));
+            if (bbk::launch_persistent(P->nb, P->prec, a, wg, s) != hipSuccess) return BB_EHIP;
+        } else {
+            a.units = (const int2*)(blob + P->off_ul);
+            for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
+                int32_t b = P->level_off[l], e = P->level_off[l + 1];
+                if (bbk::launch_level(P->nb, P->prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
+            }
+        }
+    }
+    if (timed && hipEventRecord(P->ev1, s) != hipSuccess) return BB_EHIP;
+    P->timed = timed;
+    return BB_OK;
+}
+
+// The plan applying side (0: Q, 1: P), transposed or not, to ncols columns.
+int get_apply(bb_plan* P, int side, int transpose, int64_t ncols, bb_plan** out) {
+    const int64_t jc = (ncols + P->nb - 1) / P->nb;
+    if (jc > (1 << 20)) return BB_ENOTSUP;
+    std::lock_guard<std::mutex> lk(P->apply_mu);
+    auto key = std::make_tuple(side, transpose, jc);
+    auto it = P->apply.find(key);
+    if (it != P->apply.end()) {
+        *out = it->second;
+        return BB_OK;
+    }
+    bb_plan* Q = new (std::nothrow) bb_plan();
+    if (!Q) return BB_ENOMEM;
+    Q->m = side == 0 ? P->m : P->n;
+    Q->n = jc * P->nb;
+    Q->nb = P->nb;
+    Q->tree = P->tree;
+    Q->variant = P->variant;
+    Q->prec = BB_F64;
+    Q->opts = P->opts;
+    try {
+        bb::build_apply_graph(P->g, side, transpose, (int)jc, Q->g);
+        int rc = build_schedule(*Q);
+        if (rc != BB_OK) {
+            delete Q;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete Q;
+        return BB_ENOMEM;
+    }
+    P->apply[key] = Q;
+    *out = Q;
     return BB_OK;
 }
 
@@ -269,6 +396,12 @@ std::vector<double> cache_key(int64_t m, int64_t n, int nb, int tree, int varian
 }
 
 }  // namespace
+
+bb_batch::~bb_batch() {
+    for (Group& g : groups) bb_plan_destroy(g.plan);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+}
 
 extern "C" {
 
@@ -339,6 +472,7 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
 
 void bb_plan_destroy(bb_plan* P) {
     if (!P) return;
+    for (auto& kv : P->apply) bb_plan_destroy(kv.second);
     if (P->dblob) (void)hipFree(P->dblob);
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
@@ -403,49 +537,56 @@ int bb_execute(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void
     if (vt_bytes < vt_bytes_of(*P)) return BB_EWORKSPACE;
     if (!ws) return -6;
     if (ws_bytes < ws_bytes_of(*P)) return BB_EWORKSPACE;
-    int rc = ensure_device(*P);
+    const bbk::MatDesc d0{(double*)A, lda, P->m, P->n};
+    return launch_plan(*P, &d0, vt, ws, stream);
+}
+
+int bb_apply_workspace(bb_plan* P, int side, int transpose, int64_t ncols, size_t* ws_bytes) {
+    if (!P) return -1;
+    if (side != 0 && side != 1) return -2;
+    if (transpose != 0 && transpose != 1) return -3;
+    if (ncols < 0) return -4;
+    if (!ws_bytes) return -5;
+    if (ncols == 0) {
+        *ws_bytes = 0;
+        return BB_OK;
+    }
+    bb_plan* Q = nullptr;
+    int rc = get_apply(P, side, transpose, ncols, &Q);
     if (rc != BB_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
-
-    bbk::KArgs a{};
-    a.A = (double*)A;
-    a.lda = lda;
-    a.m = P->m;
-    a.n = P->n;
-    a.vt = (double*)vt;
-    a.slot_stride = bbk::record_doubles(P->nb);
-    char* blob = (char*)P->dblob;
-    a.tasks = (const bbk::DevTask*)(blob + P->off_tasks);
-    a.nunits = (int32_t)(P->units_ticket.size() / 2);
-    a.succ_off = (const int32_t*)(blob + P->off_succ_off);
-    a.succ_idx = (const int32_t*)(blob + P->off_succ_idx);
-    a.ctrl = (int32_t*)ws;
-    a.deps = (int32_t*)((char*)ws + round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256));
-    a.watchdog_ticks = (int64_t)(P->opts.watchdog_s * P->wallclock_khz * 1000.0);
-
-    const bool timed = (P->opts.flags & BB_FLAG_TIMING) != 0;
-    if (timed && !P->ev0) {
-        if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
-    }
-    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), s) !=
-        hipSuccess)
-        return BB_EHIP;
-    if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
-    if (P->opts.sched == BB_SCHED_PERSISTENT) {
-        a.units = (const int2*)(blob + P->off_ut);
-        int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
-        if (wg < 1) wg = 1;
-        if (bbk::launch_persistent(P->nb, P->prec, a, wg, s) != hipSuccess) return BB_EHIP;
-    } else {
-        a.units = (const int2*)(blob + P->off_ul);
-        for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
-            int32_t b = P->level_off[l], e = P->level_off[l + 1];
-            if (bbk::launch_level(P->nb, P->prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
-        }
-    }
-    if (timed && hipEventRecord(P->ev1, s) != hipSuccess) return BB_EHIP;
-    P->timed = timed;
+    *ws_bytes = ws_bytes_of(*Q);
     return BB_OK;
+}
+
+static int apply_side(bb_plan* P, int side, int transpose, const void* vt, size_t vt_bytes, void* C,
+                      int64_t ldc, int64_t ncols, void* ws, size_t ws_bytes, void* stream) {
+    if (!P) return -1;
+    if (transpose != 0 && transpose != 1) return -2;
+    if (!vt) return -3;
+    if (vt_bytes < vt_bytes_of(*P)) return BB_EWORKSPACE;
+    const int64_t rows = side == 0 ? P->m : P->n;
+    if (ncols < 0) return -7;
+    if (ncols == 0) return BB_OK;
+    if (!C) return -5;
+    if (ldc < std::max<int64_t>(1, rows)) return -6;
+    if (!ws) return -8;
+    bb_plan* Q = nullptr;
+    int rc = get_apply(P, side, transpose, ncols, &Q);
+    if (rc != BB_OK) return rc;
+    if (ws_bytes < ws_bytes_of(*Q)) return BB_EWORKSPACE;
+    // exact column count: the last tile column is masked
+    const bbk::MatDesc d0{(double*)C, ldc, rows, ncols};
+    return launch_plan(*Q, &d0, const_cast<void*>(vt), ws, stream);
+}
+
+int bb_apply_q(bb_plan* P, int transpose, const void* vt, size_t vt_bytes, void* C, int64_t ldc,
+               int64_t ncols, void* ws, size_t ws_bytes, void* stream) {
+    return apply_side(P, 0, transpose, vt, vt_bytes, C, ldc, ncols, ws, ws_bytes, stream);
+}
+
+int bb_apply_p(bb_plan* P, int transpose, const void* vt, size_t vt_bytes, void* C, int64_t ldc,
+               int64_t ncols, void* ws, size_t ws_bytes, void* stream) {
+    return apply_side(P, 1, transpose, vt, vt_bytes, C, ldc, ncols, ws, ws_bytes, stream);
 }
 
 int bb_plan_last_kernel_ms(bb_plan* P, double* ms) {
@@ -552,6 +693,299 @@ double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int wor
         return -1.0;
     }
     return bb::critical_path(g, bb::kTable1Weights);
+}
+
+int bb_tuned_config(int64_t m, int64_t n, int prec, int* nb, int* tree, int* variant) {
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (prec != BB_F64 && prec != BB_F64_UPD_F32 && prec != BB_F64_UPD_SPLIT32) return -3;
+    if (!nb || !tree || !variant) return -4;
+    if (m < n) return BB_ENOTSUP;
+    const int64_t r = (1000 * n + m - 1) / m;      // ceil(1000 n / m), in (0, 1000]
+    const int* best = kTunedTable[0];
+    for (const auto& row : kTunedTable) {
+        if (m >= row[0] && m < row[1] && r > row[2] && r <= row[3]) {
+            best = row;
+            break;
+        }
+    }
+    *nb = best[4];
+    *tree = best[5];
+    *variant = best[6];
+    return BB_OK;
+}
+
+int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int64_t* n, const int* nb,
+                    const int* tree, const int* variant, int prec, const bb_opts* opts) {
+    if (!batch) return -1;
+    *batch = nullptr;
+    if (count < 0 || count > (1 << 24)) return -2;
+    if (count > 0 && !m) return -3;
+    if (count > 0 && !n) return -4;
+    if (prec != BB_F64 && prec != BB_F64_UPD_F32 && prec != BB_F64_UPD_SPLIT32) return -8;
+    bb_opts o = resolved_opts(opts);
+    if (o.sched != BB_SCHED_PERSISTENT && o.sched != BB_SCHED_LEVELS) return -9;
+    if (o.workgroups <= 0) o.workgroups = default_workgroups();
+    bb_batch* B = new (std::nothrow) bb_batch();
+    if (!B) return BB_ENOMEM;
+    B->count = count;
+    B->prec = prec;
+    B->opts = o;
+    try {
+        B->m.assign(m, m + count);
+        B->n.assign(n, n + count);
+        B->nb.resize(count);
+        B->tree.resize(count);
+        B->variant.resize(count);
+        for (int64_t i = 0; i < count; ++i) {
+            if (B->m[i] < 1 || B->n[i] < 1) { delete B; return -3; }
+            if (B->m[i] < B->n[i]) { delete B; return BB_ENOTSUP; }
+            if (!nb || nb[i] == 0) {
+                bb_tuned_config(B->m[i], B->n[i], prec, &B->nb[i], &B->tree[i], &B->variant[i]);
+            } else {
+                B->nb[i] = nb[i];
+                B->tree[i] = tree ? tree[i] : BB_GREEDY;
+                B->variant[i] = variant ? variant[i] : BB_BIDIAG;
+            }
+            if (!bbk::nb_supported(B->nb[i])) { delete B; return BB_ENOTSUP; }
+            if (B->tree[i] < BB_FLATTS || B->tree[i] > BB_AUTO) { delete B; return -6; }
+            if (B->variant[i] < BB_BIDIAG || B->variant[i] > BB_QRONLY) { delete B; return -7; }
+            if ((B->m[i] + B->nb[i] - 1) / B->nb[i] > (1 << 20)) { delete B; return BB_ENOTSUP; }
+        }
+        B->rec_off.assign(count, 0);
+        B->nrec.assign(count, 0);
+        const size_t wsg = 256;
+        for (int tile : {32, 64, 128}) {
+            std::vector<int64_t> idx;
+            for (int64_t i = 0; i < count; ++i)
+                if (B->nb[i] == tile) idx.push_back(i);
+            if (idx.empty()) continue;
+            bb_plan* P = new bb_plan();
+            bb_batch::Group grp;
+            grp.nb = tile;
+            grp.plan = P;
+            B->groups.push_back(grp);       // owned by B from here on
+            P->nb = tile;
+            P->prec = prec;
+            P->opts = o;
+            P->nmats = (int32_t)idx.size();
+            P->gidx = idx;
+            P->dims.resize(2 * idx.size());
+            const size_t rec_bytes = (size_t)bbk::record_doubles(tile) * sizeof(double);
+            for (size_t li = 0; li < idx.size(); ++li) {
+                const int64_t i = idx[li];
+                P->dims[2 * li] = B->m[i];
+                P->dims[2 * li + 1] = B->n[i];
+                bb::PlanOptions po;
+                po.tree = B->tree[i];
+                po.variant = B->variant[i];
+                po.workgroups = o.workgroups;
+                po.gamma = o.gamma;
+                po.auto_a = o.auto_a;
+                const int p = (int)((B->m[i] + tile - 1) / tile), q = (int)((B->n[i] + tile - 1) / tile);
+                bb::Graph gi;
+                if (!bb::build_graph(p, q, po, gi).empty()) { delete B; return BB_EDAG; }
+                {
+                    const size_t nt = gi.tasks.size();
+                    std::vector<int32_t> tk(8 * nt), off(nt + 1, 0), pidx;
+                    for (size_t t = 0; t < nt; ++t) {
+                        const bb::Task& x = gi.tasks[t];
+                        int32_t v[8] = {x.kind, x.trans, x.r1, x.c1, x.r2, x.c2, x.slot, x.step};
+                        std::copy(v, v + 8, tk.begin() + 8 * t);
+                        for (int32_t pr : gi.pred[t]) pidx.push_back(pr);
+                        off[t + 1] = (int32_t)pidx.size();
+                    }
+                    if (!bb::check_graph(p, q, (int64_t)nt, tk.data(), off.data(), pidx.data()).empty()) {
+                        delete B;
+                        return BB_EDAG;
+                    }
+                }
+                B->nrec[i] = gi.nslots;
+                B->rec_off[i] = (int64_t)P->g.nslots * (int64_t)rec_bytes;   // within the group
+                bb::append_graph(P->g, gi, (int32_t)li);
+                if (P->g.tasks.size() > (size_t)INT32_MAX / 2) { delete B; return BB_ENOTSUP; }
+            }
+            int rc = build_schedule(*P);
+            if (rc != BB_OK) { delete B; return rc; }
+        }
+        size_t vt_off = 0, ws_off = 0;
+        for (bb_batch::Group& grp : B->groups) {
+            grp.vt_off = vt_off;
+            grp.ws_off = ws_off;
+            vt_off = round_up(vt_off + vt_bytes_of(*grp.plan), 256);
+            ws_off = round_up(ws_off + ws_bytes_of(*grp.plan), wsg);
+            for (size_t li = 0; li < grp.plan->gidx.size(); ++li)
+                B->rec_off[grp.plan->gidx[li]] += (int64_t)grp.vt_off;
+        }
+        B->vt_bytes = vt_off;
+        B->ws_bytes = ws_off;
+    } catch (const std::bad_alloc&) {
+        delete B;
+        return BB_ENOMEM;
+    } catch (...) {
+        delete B;
+        return BB_EDAG;
+    }
+    *batch = B;
+    return BB_OK;
+}
+
+void bb_batch_destroy(bb_batch* B) { delete B; }
+
+int bb_batch_workspace(const bb_batch* B, size_t* vt_bytes, size_t* ws_bytes) {
+    if (!B) return -1;
+    if (vt_bytes) *vt_bytes = B->vt_bytes;
+    if (ws_bytes) *ws_bytes = B->ws_bytes;
+    return BB_OK;
+}
+
+int bb_batch_info(const bb_batch* B, int64_t i, int* nb, int* tree, int* variant, int64_t* rec_offset,
+                  int64_t* nrec) {
+    if (!B) return -1;
+    if (i < 0 || i >= B->count) return -2;
+    if (nb) *nb = B->nb[i];
+    if (tree) *tree = B->tree[i];
+    if (variant) *variant = B->variant[i];
+    if (rec_offset) *rec_offset = B->rec_off[i];
+    if (nrec) *nrec = B->nrec[i];
+    return BB_OK;
+}
+
+int bb_batch_execute(bb_batch* B, double* const* A, const int64_t* lda, void* vt, size_t vt_bytes,
+                     void* ws, size_t ws_bytes, void* stream) {
+    if (!B) return -1;
+    if (B->count == 0) return BB_OK;
+    if (!A) return -2;
+    if (!lda) return -3;
+    if (!vt) return -4;
+    if (vt_bytes < B->vt_bytes) return BB_EWORKSPACE;
+    if (!ws) return -6;
+    if (ws_bytes < B->ws_bytes) return BB_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const bool timed = (B->opts.flags & BB_FLAG_TIMING) != 0;
+    if (timed && !B->ev0) {
+        if (hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess) return BB_EHIP;
+    }
+    if (timed && hipEventRecord(B->ev0, s) != hipSuccess) return BB_EHIP;
+    for (bb_batch::Group& grp : B->groups) {
+        bb_plan& P = *grp.plan;
+        int rc = ensure_device(P);
+        if (rc != BB_OK) return rc;
+        char* w = (char*)ws + grp.ws_off;
+        char* blob = (char*)P.dblob;
+        if (bbk::launch_batch_desc((bbk::MatDesc*)(w + ws_mats_off()), P.nmats,
+                                   (const int64_t*)(blob + P.off_gidx), (const int64_t*)(blob + P.off_dims),
+                                   A, lda, s) != hipSuccess)
+            return BB_EHIP;
+        rc = launch_plan(P, nullptr, (char*)vt + grp.vt_off, w, stream);
+        if (rc != BB_OK) return rc;
+    }
+    if (timed && hipEventRecord(B->ev1, s) != hipSuccess) return BB_EHIP;
+    B->timed = timed;
+    return BB_OK;
+}
+
+int bb_batch_last_kernel_ms(bb_batch* B, double* ms) {
+    if (!B) return -1;
+    if (!ms) return -2;
+    if (!B->timed || !B->ev0) return BB_ENOTSUP;
+    if (hipEventSynchronize(B->ev1) != hipSuccess) return BB_EHIP;
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, B->ev0, B->ev1) != hipSuccess) return BB_EHIP;
+    *ms = (double)f;
+    return BB_OK;
+}
+
+int bb_batch_poll_error(const bb_batch* B, const void* ws, void* stream, int* device_status) {
+    if (!B) return -1;
+    if (!ws) return -2;
+    if (!device_status) return -4;
+    *device_status = 0;
+    for (const bb_batch::Group& grp : B->groups) {
+        int st = 0;
+        int rc = bb_poll_error((const char*)ws + grp.ws_off, stream, &st);
+        if (rc != BB_OK) return rc;
+        if (st != 0) {
+            *device_status = st;
+            break;
+        }
+    }
+    return BB_OK;
+}
+
+int bb_query_batched(int64_t count, const int64_t* m, const int64_t* n, const int* nb, const int* tree,
+                     const int* variant, int prec, const bb_opts* opts, size_t* vt_bytes, size_t* ws_bytes) {
+    bb_batch* B = nullptr;
+    int rc = bb_batch_create(&B, count, m, n, nb, tree, variant, prec, opts);
+    if (rc != BB_OK) return rc < 0 ? rc + 1 : rc;
+    bb_batch_workspace(B, vt_bytes, ws_bytes);
+    bb_batch_destroy(B);
+    return BB_OK;
+}
+
+namespace {
+std::mutex g_bcache_mu;
+std::map<std::vector<int64_t>, bb_batch*> g_bcache;
+}  // namespace
+
+int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, const int64_t* m,
+                        const int64_t* n, const int* nb, const int* tree, const int* variant, int prec,
+                        void* vt, size_t vt_bytes, void* ws, size_t ws_bytes, const bb_opts* opts,
+                        void* stream) {
+    if (count < 0) return -3;
+    if (count == 0) return BB_OK;
+    if (!A) return -1;
+    if (!lda) return -2;
+    if (!m) return -4;
+    if (!n) return -5;
+    bb_opts o = resolved_opts(opts);
+    std::vector<int64_t> key;
+    try {
+        key.reserve(5 * (size_t)count + 8);
+        key.push_back(prec);
+        key.push_back(o.workgroups);
+        key.push_back((int64_t)(o.gamma * 1e6));
+        key.push_back(o.auto_a);
+        key.push_back(o.sched);
+        key.push_back((int64_t)(o.watchdog_s * 1e3));
+        key.push_back(o.flags);
+        for (int64_t i = 0; i < count; ++i) {
+            key.push_back(m[i]);
+            key.push_back(n[i]);
+            key.push_back(nb ? nb[i] : 0);
+            key.push_back(tree ? tree[i] : -1);
+            key.push_back(variant ? variant[i] : -1);
+        }
+    } catch (const std::bad_alloc&) {
+        return BB_ENOMEM;
+    }
+    bb_batch* B = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_bcache_mu);
+        auto it = g_bcache.find(key);
+        if (it != g_bcache.end()) {
+            B = it->second;
+        } else {
+            int rc = bb_batch_create(&B, count, m, n, nb, tree, variant, prec, &o);
+            if (rc != BB_OK) {
+                if (rc < 0) {
+                    // bb_batch_create numbering -> this entry point's
+                    static const int remap[10] = {0, 0, -3, -4, -5, -6, -7, -8, -9, -14};
+                    return rc >= -9 ? remap[-rc] : rc;
+                }
+                return rc;
+            }
+            g_bcache[key] = B;
+        }
+    }
+    int rc = bb_batch_execute(B, A, lda, vt, vt_bytes, ws, ws_bytes, stream);
+    switch (rc) {
+    case -2: return -1;
+    case -3: return -2;
+    case -4: return -10;
+    case -6: return -12;
+    default: return rc;
+    }
 }
 
 const char* bb_strerror(int code) {

@@ -30,7 +30,7 @@ namespace {
 constexpr int NT = 256;          // threads per workgroup
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-enum : int { K_GEQRT = 0, K_TSQRT = 1, K_TTQRT = 2, K_UNMQR = 3, K_TSMQR = 4, K_TTMQR = 5 };
+enum : int { K_GEQRT = 0, K_TSQRT = 1, K_TTQRT = 2, K_UNMQR = 3, K_TSMQR = 4, K_TTMQR = 5, K_HQ = 3 };
 
 template <int NB>
 struct Shape {
@@ -86,13 +86,15 @@ struct TileView {
     }
 };
 
-__device__ __forceinline__ TileView view(const KArgs& a, int pr, int pc, int trans, int nb) {
+__device__ __forceinline__ TileView view(const KArgs& a, const DevTask& tk, int pr, int pc, int nb) {
+    const MatDesc d = a.mats[tk.mat];
+    const int trans = tk.trans & 1;
     TileView t;
-    t.base = a.A + (int64_t)pr * nb + (int64_t)pc * nb * a.lda;
-    t.ld = a.lda;
+    t.base = d.A + (int64_t)pr * nb + (int64_t)pc * nb * d.lda;
+    t.ld = d.lda;
     t.trans = trans;
-    int prow = (int)min((int64_t)nb, a.m - (int64_t)pr * nb);
-    int pcol = (int)min((int64_t)nb, a.n - (int64_t)pc * nb);
+    int prow = (int)min((int64_t)nb, d.m - (int64_t)pr * nb);
+    int pcol = (int)min((int64_t)nb, d.n - (int64_t)pc * nb);
     t.vr = trans ? pcol : prow;
     t.vc = trans ? prow : pcol;
     return t;
@@ -214,8 +216,8 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int lj = tid >> 4, lq = tid & 15; // leaf column, row phase
 
-    const TileView T1 = view(a, tk.r1, tk.c1, tk.trans, NB);
-    const TileView TX = PAIR ? view(a, tk.r2, tk.c2, tk.trans, NB) : T1;
+    const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
+    const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
     double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
     double* gV = rec;
     double* gVt = rec + NB * NB;
@@ -400,9 +402,11 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 //   C1(block-row b) -= W,   C2 -= V_b W
 // which is Q^T [C1; C2] for Q = Q_0 Q_1 ... (Section 3.2).  Zero 16 x 16
 // blocks of V are skipped: V is unit lower triangular after GEQRT and upper
-// triangular after TTQRT.
+// triangular after TTQRT.  HQ applies Q itself (used to form Q C and P C
+// from the records): the blocks in reverse order, each with T_b instead of
+// T_b^T.
 // ---------------------------------------------------------------------------
-template <int NB, int KIND, bool CO>
+template <int NB, int KIND, bool CO, bool HQ>
 __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds) {
     constexpr int MT = NB / 16;
     constexpr int NS = NB >= 64 ? 64 : NB;
@@ -412,8 +416,8 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int c0 = part * NS + 16 * w;
-    const TileView T2 = view(a, tk.r2, tk.c2, tk.trans, NB);
-    const TileView T1 = HASC1 ? view(a, tk.r1, tk.c1, tk.trans, NB) : T2;
+    const TileView T2 = view(a, tk, tk.r2, tk.c2, NB);
+    const TileView T1 = HASC1 ? view(a, tk, tk.r1, tk.c1, NB) : T2;
     // Waves without columns still take part in staging and barriers.
     const bool active = 16 * w < NS && c0 < T2.vc;
     const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
@@ -425,8 +429,8 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
         for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
         pre[PRE - 1] = rec.ld(8 * tid, 8 * (2 * NB * NB + 256 * b));
     };
-    auto stage = [&](int b, const double (&pre)[PRE]) {
-        double* buf = lds + (b & 1) * BUF;
+    auto stage = [&](int buffer, const double (&pre)[PRE]) {
+        double* buf = lds + buffer * BUF;
 #pragma unroll
         for (int k = 0; k < PRE - 1; ++k) {
             const int e = tid + 256 * k;
@@ -434,22 +438,24 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
         }
         buf[16 * LDV + tid] = pre[PRE - 1];
     };
+    auto blk = [](int step) { return HQ ? MT - 1 - step : step; };
 
     d4 c2[MT];
     if (active) load_slice<MT>(T2, c0, c2);
     double pre[PRE];
-    fetch(0, pre);
+    fetch(blk(0), pre);
     stage(0, pre);
     d4 C1n = {0.0, 0.0, 0.0, 0.0};
-    if (HASC1 && active) C1n = load16(T1, 0, c0);
+    if (HASC1 && active) C1n = load16(T1, 16 * blk(0), c0);
     lds_barrier();
 #pragma unroll
-    for (int b = 0; b < MT; ++b) {
-        const double* Vs = lds + (b & 1) * BUF;
+    for (int st = 0; st < MT; ++st) {
+        const int b = blk(st);
+        const double* Vs = lds + (st & 1) * BUF;
         const double* Ts = Vs + 16 * LDV;
-        if (b + 1 < MT) fetch(b + 1, pre);
+        if (st + 1 < MT) fetch(blk(st + 1), pre);
         const d4 C1b = C1n;
-        if (HASC1 && active && b + 1 < MT) C1n = load16(T1, 16 * (b + 1), c0);
+        if (HASC1 && active && st + 1 < MT) C1n = load16(T1, 16 * blk(st + 1), c0);
         if (active) {
             // Two accumulators halve the dependent-MFMA chain of W.
             d4 Wp[2] = {C1b, {0.0, 0.0, 0.0, 0.0}};
@@ -463,8 +469,10 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
             }
             const d4 W = Wp[0] + Wp[1];
             d4 W2 = {0.0, 0.0, 0.0, 0.0};
+            // Ts holds T_b^T column-major: T_b(k, i) at i + 16 k.
 #pragma unroll
-            for (int r = 0; r < 4; ++r) W2 = mfma(Ts[j + 16 * (4 * r + g)], W[r], W2);
+            for (int r = 0; r < 4; ++r)
+                W2 = mfma(HQ ? Ts[(4 * r + g) + 16 * j] : Ts[j + 16 * (4 * r + g)], W[r], W2);
             if (HASC1) store16<CO>(T1, 16 * b, c0, C1b - W2);
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
@@ -474,7 +482,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
                 for (int r = 0; r < 4; ++r) c2[i] = mfma(-Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
             }
         }
-        if (b + 1 < MT) stage(b + 1, pre);
+        if (st + 1 < MT) stage((st + 1) & 1, pre);
         lds_barrier();
     }
     if (active) store_slice<CO, MT>(T2, c0, c2);
@@ -546,8 +554,8 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int c0 = part * NS + 16 * w;
-    const TileView T2 = view(a, tk.r2, tk.c2, tk.trans, NB);
-    const TileView T1 = HASC1 ? view(a, tk.r1, tk.c1, tk.trans, NB) : T2;
+    const TileView T2 = view(a, tk, tk.r2, tk.c2, NB);
+    const TileView T1 = HASC1 ? view(a, tk, tk.r1, tk.c1, NB) : T2;
     const bool active = 16 * w < NS && c0 < T2.vc;
     const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
     float* fl = reinterpret_cast<float*>(lds);
@@ -657,16 +665,27 @@ __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, dou
     case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds); break;
     case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds); break;
     case K_UNMQR:
-        if (PREC == 0) update<NB, K_UNMQR, CO>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_UNMQR, CO, false>(a, tk, part, lds);
         else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds);
         break;
     case K_TSMQR:
-        if (PREC == 0) update<NB, K_TSMQR, CO>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_TSMQR, CO, false>(a, tk, part, lds);
         else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds);
         break;
-    default:
-        if (PREC == 0) update<NB, K_TTMQR, CO>(a, tk, part, lds);
+    case K_TTMQR:
+        if (PREC == 0) update<NB, K_TTMQR, CO, false>(a, tk, part, lds);
         else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds);
+        break;
+    // Applications of Q itself (records of a finished reduction, FP64 only;
+    // the host builds them for PREC 0 alone).
+    case K_UNMQR + K_HQ:
+        if (PREC == 0) update<NB, K_UNMQR, CO, true>(a, tk, part, lds);
+        break;
+    case K_TSMQR + K_HQ:
+        if (PREC == 0) update<NB, K_TSMQR, CO, true>(a, tk, part, lds);
+        break;
+    default:
+        if (PREC == 0) update<NB, K_TTMQR, CO, true>(a, tk, part, lds);
         break;
     }
 }
@@ -747,17 +766,38 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
     }
 }
 
-__global__ void init_kernel(int32_t* deps, const int32_t* ndeps, int32_t ntasks, int32_t* ctrl) {
+__global__ void init_kernel(int32_t* deps, const int32_t* ndeps, int32_t ntasks, int32_t* ctrl,
+                            MatDesc d0, MatDesc* mats, int write_d0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < CTRL_WORDS) ctrl[i] = 0;
+    if (write_d0 && i == 0) mats[0] = d0;
     for (int t = i; t < ntasks; t += gridDim.x * blockDim.x) deps[t] = ndeps[t];
 }
 
-hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s) {
+hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, const MatDesc* d0,
+                       hipStream_t s) {
     int blocks = (ntasks + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, a.deps, ndeps_init, ntasks, a.ctrl);
+    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, a.deps, ndeps_init, ntasks, a.ctrl,
+                       d0 ? *d0 : MatDesc{}, const_cast<MatDesc*>(a.mats), d0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void batch_desc_kernel(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
+                                  double* const* A, const int64_t* lda) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmats; i += gridDim.x * blockDim.x) {
+        const int64_t g = gidx[i];
+        mats[i] = MatDesc{A[g], lda[g], dims[2 * i], dims[2 * i + 1]};
+    }
+}
+
+hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
+                             double* const* A, const int64_t* lda, hipStream_t s) {
+    if (nmats <= 0) return hipSuccess;
+    int blocks = (nmats + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(batch_desc_kernel, dim3(blocks), dim3(256), 0, s, mats, nmats, gidx, dims, A, lda);
     return hipGetLastError();
 }
 

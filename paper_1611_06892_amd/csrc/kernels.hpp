@@ -6,17 +6,23 @@
 
 namespace bbk {
 
-// One task of the graph as the device reads it (physical tile coordinates).
+// One task of the graph as the device reads it (physical tile coordinates of
+// matrix `mat` of the launch).
 struct DevTask {
-    int32_t kind, trans, r1, c1, r2, c2, slot, nparts;
+    int32_t kind, trans, r1, c1, r2, c2, slot, mat;
+};
+
+// One matrix of a launch: column-major, m x n, leading dimension lda.
+struct MatDesc {
+    double* A;
+    int64_t lda, m, n;
 };
 
 // Scheduler control words at the start of the workspace.
 enum : int { CTRL_TICKET = 0, CTRL_ERROR = 1, CTRL_DONE = 2, CTRL_WORDS = 64 };
 
 struct KArgs {
-    double* A;
-    int64_t lda, m, n;
+    const MatDesc* mats;     // matrices of the launch (in the workspace)
     double* vt;              // V/T records
     int64_t slot_stride;     // doubles per record (record_doubles(nb))
     const DevTask* tasks;
@@ -36,7 +42,15 @@ inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
 inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
-hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
+// Resets the scheduler words and dependency counters; with d0 != NULL also
+// writes *d0 as the launch's only matrix descriptor (a.mats[0]).
+hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, const MatDesc* d0,
+                       hipStream_t s);
+// Fills mats[i] = {A[gidx[i]], lda[gidx[i]], dims[2i], dims[2i+1]} for the
+// nmats matrices of one group of a batched launch (A, lda: the caller's device
+// arrays; gidx, dims: the plan's device copy).
+hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
+                             double* const* A, const int64_t* lda, hipStream_t s);
 // prec: 0 = FP64, 2 = FP32-MFMA updates, 3 = split-FP32 updates (bidiag.h's BB_F64*).
 hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
 hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s);

@@ -264,6 +264,72 @@ std::string check_graph(int p, int q, int64_t nt, const int32_t* tk, const int32
     return std::string();
 }
 
+void build_apply_graph(const Graph& g, int side, int transpose, int jc, Graph& out) {
+    const int rows = side == 0 ? g.p : g.q;
+    out = Graph();
+    out.p = rows;
+    out.q = jc;
+    out.opt = g.opt;
+    out.nslots = g.nslots;
+    std::vector<int32_t> panels;
+    for (size_t t = 0; t < g.tasks.size(); ++t)
+        if (is_panel(g.tasks[t].kind) && g.tasks[t].trans == side) panels.push_back((int32_t)t);
+    if (!transpose) std::reverse(panels.begin(), panels.end());
+    std::vector<int32_t> last((size_t)rows * jc, -1);
+    out.tasks.reserve(panels.size() * (size_t)jc);
+    out.pred.reserve(panels.size() * (size_t)jc);
+    for (int32_t pt : panels) {
+        const Task& x = g.tasks[pt];
+        // Rows of C that the reflectors act on: the physical tile rows of a
+        // QR-step panel, the physical tile columns of an LQ-step panel.
+        const int32_t a1 = side == 0 ? x.r1 : x.c1;
+        const int32_t a2 = x.kind == GEQRT ? -1 : (side == 0 ? x.r2 : x.c2);
+        const int32_t kind = x.kind + 3 + (transpose ? 0 : APPLY_H);   // GEQRT -> UNMQR, ...
+        for (int J = 0; J < jc; ++J) {
+            Task u{};
+            u.kind = kind;
+            u.trans = 0;
+            u.slot = x.slot;
+            u.step = x.step;
+            if (x.kind == GEQRT) {          // UNMQR: C2 is the panel's own tile row
+                u.r1 = -1; u.c1 = -1; u.r2 = a1; u.c2 = J;
+            } else {
+                u.r1 = a1; u.c1 = J; u.r2 = a2; u.c2 = J;
+            }
+            const int32_t id = (int32_t)out.tasks.size();
+            std::vector<int32_t> pr;
+            for (int32_t r : {u.r1, u.r2}) {
+                if (r < 0) continue;
+                int32_t& l = last[(size_t)r * jc + J];
+                if (l >= 0) pr.push_back(l);
+                l = id;
+            }
+            std::sort(pr.begin(), pr.end());
+            pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+            out.tasks.push_back(u);
+            out.pred.push_back(std::move(pr));
+        }
+    }
+}
+
+void append_graph(Graph& g, const Graph& h, int32_t mat) {
+    const int32_t t0 = (int32_t)g.tasks.size();
+    const int32_t s0 = g.nslots;
+    g.p = std::max(g.p, h.p);
+    g.q = std::max(g.q, h.q);
+    for (size_t t = 0; t < h.tasks.size(); ++t) {
+        Task x = h.tasks[t];
+        x.slot += s0;
+        x.mat = mat;
+        g.tasks.push_back(x);
+        std::vector<int32_t> pr(h.pred[t]);
+        for (int32_t& v : pr) v += t0;
+        g.pred.push_back(std::move(pr));
+    }
+    g.nslots += h.nslots;
+    g.nsteps = std::max(g.nsteps, h.nsteps);
+}
+
 double critical_path(const Graph& g, const double* w) {
     std::vector<double> fin(g.tasks.size(), 0.0);
     double best = 0.0;

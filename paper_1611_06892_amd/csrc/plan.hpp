@@ -23,6 +23,9 @@
 namespace bb {
 
 enum Kind : int { GEQRT = 0, TSQRT = 1, TTQRT = 2, UNMQR = 3, TSMQR = 4, TTMQR = 5 };
+// Updates that apply H = I - V T V^T itself instead of H^T (blocks of the
+// record in reverse order, T instead of T^T): UNMQR + APPLY_H, ...
+enum : int { APPLY_H = 3, NKINDS = 9 };
 enum Tree : int { FLATTS = 0, FLATTT = 1, GREEDY = 2, AUTO = 3 };
 // QRONLY is the tiled QR factorization QR(p,q) of Algorithm 1 alone (the first
 // phase of R-BiDiag); it exists for the critical-path formulas of Section 4.3.
@@ -41,6 +44,7 @@ struct Task {
     int32_t r1, c1, r2, c2;
     int32_t slot;    // V/T slot written (panel) or read (update)
     int32_t step;    // index of the QR/LQ step this task belongs to
+    int32_t mat;     // matrix of a batched graph (0 otherwise)
 };
 
 struct PlanOptions {
@@ -67,6 +71,22 @@ std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g);
 // Table 1 weights in units of nb^3/3 flops: GEQRT 4, TSQRT 6, TTQRT 2,
 // UNMQR 6, TSMQR 12, TTMQR 6.
 extern const double kTable1Weights[6];
+
+// Graph that applies the reflectors recorded by a reduction graph g to a
+// matrix C whose rows are the tile rows (side 0, Q) or the tile columns
+// (side 1, P) of the reduced matrix, with jc tile columns.  The forward
+// applies H_1^T, H_2^T, ... (panels in program order), so Q = H_1 H_2 ... over
+// the QR-step panels (trans 0) and P = G_1 G_2 ... over the LQ-step panels
+// (trans 1), with B = Q^T A P (Sections 3.4, 3.5).  transpose = 1 builds
+// C <- Q^T C (P^T C): every panel's update in program order;  transpose = 0
+// builds C <- Q C (P C): the panels in reverse order with APPLY_H kinds.
+// Tasks carry trans 0 (C is not transposed) and the panel's slot; each
+// depends on the previous task that touched one of its C tiles.
+void build_apply_graph(const Graph& g, int side, int transpose, int jc, Graph& out);
+
+// Appends graph h (of matrix `mat`) to the union graph g of a batch: task
+// indices, predecessors and slots are offset; no edge joins two matrices.
+void append_graph(Graph& g, const Graph& h, int32_t mat);
 
 // Static race check of a task graph given as arrays (program order):
 // predecessors precede their task; every two consecutive tasks touching the

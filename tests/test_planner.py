@@ -213,3 +213,101 @@ def test_generated_graphs_are_race_free_and_mutations_are_caught():
         off3[1:] += 1
         idx3 = np.concatenate([[len(tasks) - 1], idx])
         assert bb.graph_check(st["p"], st["q"], tasks, off3, idx3) == 4
+
+
+def test_apply_workspace_and_argument_errors():
+    """bb_apply_q / bb_apply_p: one update task per (panel of the side, tile
+    column of C); argument errors are reported before any device work."""
+    L = bb.lib()
+    p = bb.Plan(300, 200, 64, "greedy", "bidiag")
+    tasks, _, _ = p.export()
+    panels = tasks[tasks[:, 0] <= 2]
+    vt, _ = p.workspace()
+    for side, ncols in ((0, 200), (1, 200), (0, 7), (1, 129)):
+        npan = int(np.sum(panels[:, 1] == side))
+        jc = -(-ncols // 64)
+        expect = 512 + -(-(4 * npan * jc) // 256) * 256
+        for tr in (0, 1):
+            assert p.apply_workspace(side, tr, ncols) == expect
+    assert p.apply_workspace(0, 0, 0) == 0
+    v8 = ctypes.c_void_p(8)
+    ws = p.apply_workspace(0, 0, 5)
+    assert L.bb_apply_q(None, 0, v8, vt, v8, 300, 5, v8, ws, None) == -1
+    assert L.bb_apply_q(p._h, 2, v8, vt, v8, 300, 5, v8, ws, None) == -2
+    assert L.bb_apply_q(p._h, 0, None, vt, v8, 300, 5, v8, ws, None) == -3
+    assert L.bb_apply_q(p._h, 0, v8, vt - 8, v8, 300, 5, v8, ws, None) == 6
+    assert L.bb_apply_q(p._h, 0, v8, vt, None, 300, 5, v8, ws, None) == -5
+    assert L.bb_apply_q(p._h, 0, v8, vt, v8, 299, 5, v8, ws, None) == -6
+    assert L.bb_apply_p(p._h, 0, v8, vt, v8, 199, 5, v8, ws, None) == -6
+    assert L.bb_apply_q(p._h, 0, v8, vt, v8, 300, -1, v8, ws, None) == -7
+    assert L.bb_apply_q(p._h, 0, v8, vt, v8, 300, 5, None, ws, None) == -8
+    assert L.bb_apply_q(p._h, 0, v8, vt, v8, 300, 5, v8, ws - 4, None) == 6
+    assert L.bb_apply_q(p._h, 0, v8, vt, v8, 300, 0, v8, 0, None) == 0
+    assert L.bb_apply_workspace(p._h, 2, 0, 5, ctypes.byref(ctypes.c_size_t())) == -2
+
+
+def test_batch_plan_layout_and_tuning_table():
+    """A batch is one graph per tile size; records of each matrix are
+    contiguous and the workspace covers every group."""
+    shapes = [(300, 200), (64, 64), (1000, 100), (129, 33), (500, 500)]
+    nbs = [64, 32, 128, 32, 64]
+    plan = bb.BatchPlan(shapes, nb=nbs, tree=["greedy", "flatts", "auto", "flattt", "greedy"],
+                        variant=["bidiag", "rbidiag", "rbidiag", "bidiag", "bidiag"])
+    vt, ws = plan.workspace()
+    total = 0
+    for i, ((m, n), nb) in enumerate(zip(shapes, nbs)):
+        info = plan.info(i)
+        assert info["nb"] == nb
+        single = bb.Plan(m, n, nb, info["tree"], info["variant"])
+        assert info["nrec"] == single.stats()["nslots"]
+        total += single.workspace()[0]
+        rec = 8 * (2 * nb * nb + 16 * nb)
+        assert info["rec_offset"] % rec == 0 or info["rec_offset"] % 256 == 0
+        assert info["rec_offset"] + info["nrec"] * rec <= vt
+    assert vt >= total
+    # records of different matrices do not overlap
+    spans = sorted((plan.info(i)["rec_offset"],
+                    plan.info(i)["rec_offset"] + plan.info(i)["nrec"] * 8 *
+                    (2 * nbs[i] ** 2 + 16 * nbs[i])) for i in range(len(shapes)))
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert a1 <= b0
+    # tuned choices are valid and cover the whole range of sizes
+    for m in (64, 100, 191, 192, 383, 384, 639, 640, 1024, 5000):
+        for n in sorted({32, m // 4, m // 4 + 1, m // 2, m // 2 + 1, m}):
+            if n < 1:
+                continue
+            nb, tree, var = bb.tuned_config(m, n)
+            assert nb in (32, 64, 128) and tree in bb.TREES and var in ("bidiag", "rbidiag")
+    tuned = bb.BatchPlan(shapes)
+    for i, (m, n) in enumerate(shapes):
+        assert tuned.info(i)["nb"] == bb.tuned_config(m, n)[0]
+    assert bb.BatchPlan([]).workspace() == (0, 0)
+
+
+def test_batch_argument_errors():
+    L = bb.lib()
+    h = ctypes.c_void_p()
+    m = np.array([100, 50], dtype=np.int64)
+    n = np.array([50, 60], dtype=np.int64)
+    opts = bb.make_opts()
+    assert L.bb_batch_create(ctypes.byref(h), 2, m.ctypes.data, n.ctypes.data, None, None, None, 0,
+                             ctypes.byref(opts)) == 1            # m < n
+    n[1] = 50
+    bad = np.array([64, 48], dtype=np.int32)
+    assert L.bb_batch_create(ctypes.byref(h), 2, m.ctypes.data, n.ctypes.data, bad.ctypes.data,
+                             None, None, 0, ctypes.byref(opts)) == 1   # nb
+    assert L.bb_batch_create(ctypes.byref(h), -1, None, None, None, None, None, 0,
+                             ctypes.byref(opts)) == -2
+    assert L.bb_batch_create(ctypes.byref(h), 2, m.ctypes.data, n.ctypes.data, None, None, None, 1,
+                             ctypes.byref(opts)) == -8
+    vt, ws = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.bb_query_batched(2, m.ctypes.data, n.ctypes.data, None, None, None, 1,
+                              ctypes.byref(opts), ctypes.byref(vt), ctypes.byref(ws)) == -7
+    assert L.bb_query_batched(2, m.ctypes.data, n.ctypes.data, None, None, None, 0,
+                              ctypes.byref(opts), ctypes.byref(vt), ctypes.byref(ws)) == 0
+    p = bb.BatchPlan([(100, 50), (50, 50)])
+    assert (vt.value, ws.value) == p.workspace()
+    v8 = ctypes.c_void_p(8)
+    assert L.bb_batch_execute(p._h, None, v8, v8, vt.value, v8, ws.value, None) == -2
+    assert L.bb_batch_execute(p._h, v8, v8, v8, vt.value - 8, v8, ws.value, None) == 6
+    assert L.bb_batch_execute(p._h, v8, v8, v8, vt.value, v8, ws.value - 8, None) == 6
