@@ -188,6 +188,27 @@ int bb_apply_p(bb_plan* plan, int transpose, const void* vt, size_t vt_bytes, vo
  * given transpose and column count (host only). */
 int bb_apply_workspace(bb_plan* plan, int side, int transpose, int64_t ncols, size_t* ws_bytes);
 
+/*
+ * bidiag_band_adjoint -- gradient of L = sum_ij W(i,j) B(i,j) over the band of
+ * a finished reduction with respect to its input A (the sensitivity of
+ * B = Q^T A P, Sections 3.4 and 3.5): Abar = Q_thin G P^T, where G (n x n)
+ * solves the transposed band-constraint system of the perturbations
+ * Q^T dQ and P^T dP (block sweep over the nb-blocks of B in reverse order),
+ * and Q, P are applied from the V/T records as in bb_apply_q/p.
+ * Arguments: plan (1) of the reduction; B (2) its output (m x n, device,
+ * column-major) with ldb (3) >= m; W (4) n x n device weights, column-major,
+ * ldw (5) >= n (entries outside the band 0 <= j - i <= nb are ignored); vt (6)
+ * with vt_bytes (7): that reduction's records; Abar (8) m x n device output,
+ * ldabar (9) >= m; ws (10) / ws_bytes (11) >= bb_adjoint_workspace; stream
+ * (12).  FP64.  The gradient exists where every diagonal and super-diagonal
+ * block of B is nonsingular (true almost surely); BB_QRONLY plans return
+ * BB_ENOTSUP.
+ */
+int bidiag_band_adjoint(bb_plan* plan, const void* B, int64_t ldb, const void* W, int64_t ldw,
+                        const void* vt, size_t vt_bytes, void* Abar, int64_t ldabar, void* ws,
+                        size_t ws_bytes, void* stream);
+int bb_adjoint_workspace(bb_plan* plan, size_t* ws_bytes);
+
 /* ---- batches of independent reductions ------------------------------- */
 /*
  * A batch reduces `count` independent matrices, each by its own task graph

@@ -56,7 +56,8 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_plan_auto_domains", "bb_apply_q", "bb_apply_p", "bb_apply_workspace",
            "bb_tuned_config", "bb_batch_create", "bb_batch_destroy", "bb_batch_workspace",
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
-           "bb_query_batched", "bidiag_band_batched"]
+           "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
+           "bb_adjoint_workspace"]
 
 
 def lib():
@@ -130,6 +131,11 @@ def lib():
     L.bidiag_band_batched.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp, ctypes.c_size_t,
                                       vp, ctypes.c_size_t, ctypes.POINTER(_Opts), vp]
     L.bidiag_band_batched.restype = i32
+    L.bidiag_band_adjoint.argtypes = [P, vp, i64, vp, i64, vp, ctypes.c_size_t, vp, i64, vp,
+                                      ctypes.c_size_t, vp]
+    L.bidiag_band_adjoint.restype = i32
+    L.bb_adjoint_workspace.argtypes = [P, szp]
+    L.bb_adjoint_workspace.restype = i32
     L.bb_strerror.argtypes = [i32]
     L.bb_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -276,6 +282,29 @@ class Plan:
         ms = ctypes.c_double()
         _check(lib().bb_plan_last_kernel_ms(self._h, ctypes.byref(ms)), "bb_plan_last_kernel_ms")
         return ms.value
+
+    def adjoint_workspace(self) -> int:
+        ws = ctypes.c_size_t()
+        _check(lib().bb_adjoint_workspace(self._h, ctypes.byref(ws)), "bb_adjoint_workspace")
+        return ws.value
+
+    def adjoint(self, Bcm, ldb, W, vt, ws=None, stream=None):
+        """Gradient of sum(W * B) over the band with respect to the reduced
+        matrix: Bcm is the column-major storage of the reduction's output B
+        (leading dimension ldb), W an n x n tensor (only its band entries are
+        used).  Returns the m x n gradient (a CUDA tensor view)."""
+        import torch
+        Wcm = W.to(device=Bcm.device, dtype=torch.float64).t().contiguous()
+        Ab = torch.empty(self.n, self.m, dtype=torch.float64, device=Bcm.device)
+        if ws is None:
+            ws = torch.empty(max(self.adjoint_workspace(), 8), dtype=torch.uint8, device=Bcm.device)
+        _check(lib().bidiag_band_adjoint(self._h, ctypes.c_void_p(Bcm.data_ptr()), int(ldb),
+                                         ctypes.c_void_p(Wcm.data_ptr()), self.n,
+                                         ctypes.c_void_p(vt.data_ptr()), vt.numel(),
+                                         ctypes.c_void_p(Ab.data_ptr()), self.m,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_handle(stream)), "bidiag_band_adjoint")
+        return Ab.t()
 
 
 def poll_error(ws, stream=None) -> int:
@@ -424,3 +453,42 @@ def unpack(buf, offsets, shapes, i):
     m, n = shapes[i]
     o = int(offsets[i])
     return buf[o:o + m * n].view(n, m).t()
+
+
+def _band_function():
+    import torch
+
+    class BandBidiag(torch.autograd.Function):
+        """B = band(A) with the hand-written adjoint as backward: the gradient
+        of any loss reaches A through the band entries of B (the other entries
+        are identically zero)."""
+
+        @staticmethod
+        def forward(ctx, A, nb, tree, variant):
+            m, n = A.shape
+            plan = Plan(m, n, nb, tree, variant)
+            S = to_colmajor(A.detach())
+            vt, ws = plan.alloc(S.device)
+            plan.execute(S, m, vt, ws)
+            ctx.plan, ctx.vt, ctx.S = plan, vt, S
+            return S.t().clone()
+
+        @staticmethod
+        def backward(ctx, Bbar):
+            n = ctx.plan.n
+            Ab = ctx.plan.adjoint(ctx.S, ctx.plan.m, Bbar[:n, :n], ctx.vt)
+            return Ab.to(Bbar.dtype), None, None, None
+
+    return BandBidiag
+
+
+_BandBidiag = None
+
+
+def band_autograd(A, nb, tree="greedy", variant="rbidiag"):
+    """Differentiable band form: returns B (m x n); B.backward / autograd use
+    bidiag_band_adjoint."""
+    global _BandBidiag
+    if _BandBidiag is None:
+        _BandBidiag = _band_function()
+    return _BandBidiag.apply(A, nb, tree, variant)

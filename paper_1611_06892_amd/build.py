@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbidiag.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "api.cpp", "plan.cpp", "adjoint_ops.cpp"]
 ARCH = "gfx950"
 
 

@@ -19,6 +19,7 @@
 #include <tuple>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -48,6 +49,10 @@ struct bb_plan {
     // (side, transpose, tile columns of C).
     std::map<std::tuple<int, int, int64_t>, bb_plan*> apply;
     std::mutex apply_mu;
+    // adjoint: operation list and its device copy
+    bbk::AdjointOps* adj = nullptr;
+    void* adj_dev = nullptr;
+    int adj_device = -1;
 };
 
 // A batch: one plan (union graph) per tile size, run one after the other.
@@ -473,6 +478,8 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
 void bb_plan_destroy(bb_plan* P) {
     if (!P) return;
     for (auto& kv : P->apply) bb_plan_destroy(kv.second);
+    delete P->adj;
+    if (P->adj_dev) (void)hipFree(P->adj_dev);
     if (P->dblob) (void)hipFree(P->dblob);
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
@@ -587,6 +594,117 @@ int bb_apply_q(bb_plan* P, int transpose, const void* vt, size_t vt_bytes, void*
 int bb_apply_p(bb_plan* P, int transpose, const void* vt, size_t vt_bytes, void* C, int64_t ldc,
                int64_t ncols, void* ws, size_t ws_bytes, void* stream) {
     return apply_side(P, 1, transpose, vt, vt_bytes, C, ldc, ncols, ws, ws_bytes, stream);
+}
+
+namespace {
+
+// Workspace of the adjoint: G, G^T (n x n), the Omega and Psi bar grids
+// (npad x npad), scratch (npad x 3nb), then the apply plans' state.
+struct AdjLayout {
+    size_t g, gt, om, ps, tmp, apply, total;
+};
+
+int adjoint_layout(bb_plan* P, AdjLayout& L) {
+    const int64_t n = P->n, nb = P->nb;
+    const int64_t npad = (n + nb - 1) / nb * nb;
+    bb_plan *Qp = nullptr, *Pp = nullptr;
+    int rc = get_apply(P, 1, 0, n, &Pp);
+    if (rc != BB_OK) return rc;
+    rc = get_apply(P, 0, 0, n, &Qp);
+    if (rc != BB_OK) return rc;
+    size_t off = 0;
+    L.g = off; off = round_up(off + sizeof(double) * n * n, 256);
+    L.gt = off; off = round_up(off + sizeof(double) * n * n, 256);
+    L.om = off; off = round_up(off + sizeof(double) * npad * npad, 256);
+    L.ps = off; off = round_up(off + sizeof(double) * npad * npad, 256);
+    L.tmp = off; off = round_up(off + sizeof(double) * npad * 3 * nb, 256);
+    L.apply = off; off += std::max(ws_bytes_of(*Qp), ws_bytes_of(*Pp));
+    L.total = off;
+    return BB_OK;
+}
+
+}  // namespace
+
+int bb_adjoint_workspace(bb_plan* P, size_t* ws_bytes) {
+    if (!P) return -1;
+    if (!ws_bytes) return -2;
+    AdjLayout L;
+    int rc = adjoint_layout(P, L);
+    if (rc != BB_OK) return rc;
+    *ws_bytes = L.total;
+    return BB_OK;
+}
+
+int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, int64_t ldw, const void* vt,
+                        size_t vt_bytes, void* Abar, int64_t ldabar, void* ws, size_t ws_bytes, void* stream) {
+    if (!P) return -1;
+    if (!B) return -2;
+    if (ldb < std::max<int64_t>(1, P->m)) return -3;
+    if (!W) return -4;
+    if (ldw < std::max<int64_t>(1, P->n)) return -5;
+    if (!vt) return -6;
+    if (vt_bytes < vt_bytes_of(*P)) return BB_EWORKSPACE;
+    if (!Abar) return -8;
+    if (ldabar < std::max<int64_t>(1, P->m)) return -9;
+    if (!ws) return -10;
+    if (P->variant == BB_QRONLY) return BB_ENOTSUP;
+    AdjLayout L;
+    int rc = adjoint_layout(P, L);
+    if (rc != BB_OK) return rc;
+    if (ws_bytes < L.total) return BB_EWORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
+    try {
+        if (!P->adj) {
+            P->adj = new bbk::AdjointOps();
+            bbk::build_adjoint_ops(P->m, P->n, P->nb, *P->adj);
+        }
+    } catch (const std::bad_alloc&) {
+        return BB_ENOMEM;
+    }
+    const bbk::AdjointOps& ops = *P->adj;
+    if (!P->adj_dev || P->adj_device != dev) {
+        if (P->adj_dev) (void)hipFree(P->adj_dev);
+        P->adj_dev = nullptr;
+        const size_t bytes = ops.ops.size() * sizeof(bbk::AOp);
+        if (hipMalloc(&P->adj_dev, std::max<size_t>(bytes, 256)) != hipSuccess) return BB_ENOMEM;
+        if (hipMemcpy(P->adj_dev, ops.ops.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return BB_EHIP;
+        P->adj_device = dev;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    const int64_t n = P->n, npad = ops.npad;
+    bbk::AArgs a{};
+    a.buf[bbk::AB_B] = {(double*)B, ldb};
+    a.buf[bbk::AB_W] = {(double*)W, ldw};
+    a.buf[bbk::AB_G] = {(double*)(w + L.g), n};
+    a.buf[bbk::AB_GT] = {(double*)(w + L.gt), n};
+    a.buf[bbk::AB_OM] = {(double*)(w + L.om), npad};
+    a.buf[bbk::AB_PS] = {(double*)(w + L.ps), npad};
+    a.buf[bbk::AB_TMP] = {(double*)(w + L.tmp), npad};
+    a.buf[bbk::AB_ABAR] = {(double*)Abar, ldabar};
+    const bbk::AOp* dops = (const bbk::AOp*)P->adj_dev;
+    auto run_stages = [&](int32_t s0, int32_t s1) -> int {
+        for (int32_t st = s0; st < s1; ++st) {
+            const int32_t o0 = ops.stage_off[st], o1 = ops.stage_off[st + 1];
+            if (bbk::launch_adjoint_stage(a, dops, o0, o1, ops.ops[o0].kind, ops.stage_m[st], ops.stage_n[st], s) !=
+                hipSuccess)
+                return BB_EHIP;
+        }
+        return BB_OK;
+    };
+    const int32_t nst = (int32_t)ops.stage_off.size() - 1;
+    rc = run_stages(0, ops.finish_stage);
+    if (rc != BB_OK) return rc;
+    bb_plan *Pp = nullptr, *Qp = nullptr;
+    if ((rc = get_apply(P, 1, 0, n, &Pp)) != BB_OK) return rc;
+    if ((rc = get_apply(P, 0, 0, n, &Qp)) != BB_OK) return rc;
+    const bbk::MatDesc dP{(double*)(w + L.gt), n, n, n};
+    if ((rc = launch_plan(*Pp, &dP, const_cast<void*>(vt), w + L.apply, stream)) != BB_OK) return rc;
+    rc = run_stages(ops.finish_stage, nst);
+    if (rc != BB_OK) return rc;
+    const bbk::MatDesc dQ{(double*)Abar, ldabar, P->m, n};
+    return launch_plan(*Qp, &dQ, const_cast<void*>(vt), w + L.apply, stream);
 }
 
 int bb_plan_last_kernel_ms(bb_plan* P, double* ms) {

@@ -219,3 +219,29 @@ def test_thread_count_does_not_change_bits():
         env = dict(os.environ, OMP_NUM_THREADS=t)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env))
     assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("m,n,nb", [(40, 24, 8), (30, 30, 6), (50, 20, 16), (36, 27, 8)])
+def test_reference_gradient_matches_finite_differences(m, n, nb):
+    """The autograd gradient of block Golub-Kahan (oracle/adjoint.py) against
+    central differences of the unblocked C oracle, a different algorithm:
+    L(A) = sum(W * B~(A)) with B~ the sign-normalized band form."""
+    from oracle import adjoint
+    rng = np.random.default_rng(m * n + nb)
+    A = rng.standard_normal((m, n))
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    W = rng.standard_normal((n, n)) * ((j >= i) & (j <= i + nb))
+    B0, _ = oracle.band_reduce(A, nb)
+    Lref, G = adjoint.band_loss_gradient(A, W, nb, B0)
+
+    def L(M):       # the loss on the oracle's own (raw, not normalized) band form
+        return float(np.sum(W * oracle.band_reduce(M, nb)[0][:n]))
+
+    assert abs(L(A) - Lref) <= 1e-10 * max(1.0, abs(Lref))
+    h = 1e-6
+    for d in range(4):
+        E = rng.standard_normal((m, n))
+        fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
+        an = float(np.sum(G * E))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
