@@ -164,6 +164,74 @@ def bench_batch(args, bb, torch, np, workloads):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args, bb, torch, np, workloads):
+    """8192 x 1024 N(0,1) (seed 6), R-BiDiag Greedy, nb = 128, and the gradient
+    of sum(W * B) over the band (W N(0,1), seed 7).  One step = forward
+    reduction + adjoint, from a fresh copy of A already in HBM; HIP events on
+    the launch stream time each part."""
+    cfg = workloads.CONFIGS["adjoint"]
+    m, n, nb = cfg["m"], cfg["n"], cfg["nb"]
+    A = workloads.gaussian(m, n, cfg["seed"])
+    W = torch.as_tensor(workloads.band_weights(n, nb, cfg["wseed"])).cuda()
+    S0 = bb.to_colmajor(torch.from_numpy(A))
+    plan = bb.Plan(m, n, nb, args.tree, "rbidiag")
+    vt, ws = plan.alloc()
+    aws = torch.empty(plan.adjoint_workspace(), dtype=torch.uint8, device="cuda")
+    S = torch.empty_like(S0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fw, bw = [], []
+    Ab = None
+    for k in range(args.warmup + args.steps):
+        S.copy_(S0)
+        ev[0].record()
+        plan.execute(S, m, vt, ws)
+        ev[1].record()
+        Ab = plan.adjoint(S, m, W, vt, ws=aws)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            fw.append(ev[0].elapsed_time(ev[1]))
+            bw.append(ev[1].elapsed_time(ev[2]))
+        log("  step %d: forward %.2f ms, adjoint %.2f ms" % (k, ev[0].elapsed_time(ev[1]),
+                                                            ev[1].elapsed_time(ev[2])))
+    st = bb.poll_error(ws)
+    if st != 0:
+        raise RuntimeError("device scheduler error %d" % st)
+    # accuracy: central differences of the forward in 4 random unit directions
+    Wd = W
+    def L(M):
+        Sm = bb.to_colmajor(torch.from_numpy(M))
+        p2 = plan
+        v2, w2 = p2.alloc()
+        p2.execute(Sm, m, v2, w2)
+        return float(torch.sum(Wd * Sm.t()[:n]))
+    Ag = Ab.cpu().numpy()
+    rng = np.random.default_rng(8)
+    h = 1e-6 * np.linalg.norm(A)
+    fd_err = 0.0
+    for _ in range(4):
+        E = rng.standard_normal((m, n))
+        E /= np.linalg.norm(E)
+        fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
+        fd_err = max(fd_err, abs(fd - float(np.sum(Ag * E))) / np.linalg.norm(Ag))
+    f_ms, b_ms = float(np.median(fw)), float(np.median(bw))
+    flops = workloads.flops_bidiag(m, n)
+    out = {
+        "metric": METRIC, "value": round(flops / ((f_ms + b_ms) * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f_ms + b_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint 8192x1024 nb=128 rbidiag %s, forward + gradient of "
+                               "sum(W*B)" % args.tree, "m": m, "n": n, "nb": nb,
+                   "parallelism": "single GPU"},
+        "forward_ms": round(f_ms, 3), "adjoint_ms": round(b_ms, 3),
+        "adjoint_over_forward": round(b_ms / f_ms, 3),
+        "check": {"fd_max_err_rel_grad_norm": fd_err},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,7 +242,7 @@ def main():
     ap.add_argument("--sched", default="persistent", choices=["persistent", "levels"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f64_upd_f32", "f64_upd_split32"])
     ap.add_argument("--workload", default="tall_graded",
-                    choices=["tall_graded", "square_graded", "batch"])
+                    choices=["tall_graded", "square_graded", "batch", "adjoint"])
     ap.add_argument("--nb", type=int, default=0, help="tile size (0: the workload's)")
     ap.add_argument("--m", type=int, default=0, help="rows (0: the workload's)")
     ap.add_argument("--n", type=int, default=0, help="columns (0: the workload's)")
@@ -195,6 +263,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args, bb, torch, np, workloads)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, bb, torch, np, workloads)
     cfg = workloads.CONFIGS[args.workload]
     m, n, nb = args.m or cfg["m"], args.n or cfg["n"], args.nb or cfg["nb"]
     log("generating %d x %d graded input" % (m, n))

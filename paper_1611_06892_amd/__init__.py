@@ -318,7 +318,10 @@ def to_colmajor(A):
     """Column-major device copy of a 2-D tensor: returns the (n, m) row-major
     storage tensor S with S[j, i] = A[i, j] (so S.t() is A)."""
     import torch
-    return A.to(device="cuda", dtype=torch.float64).t().contiguous()
+    # always a copy: for a column-major FP64 CUDA input, .t().contiguous()
+    # would return a view of the caller's storage, which the reduction
+    # overwrites in place
+    return A.to(device="cuda", dtype=torch.float64).t().clone(memory_format=torch.contiguous_format)
 
 
 def band(A, nb, tree="auto", variant="bidiag", plan=None, check=True, **opts):

@@ -10,8 +10,9 @@ rebuild:
 
 Classes: rows m in [64,192), [192,384), [384,640), [640,1025) crossed with the
 aspect 1000 n/m in (0,250], (250,500], (500,1000].  Each class is sampled by
-seeded N(0,1) matrices with (m, n) uniform inside the class; the sample is
-sized to a fixed amount of work so that every candidate fills the GPU.
+seeded N(0,1) matrices with (m, n) uniform inside the class; the sample holds
+at least 256 matrices and about 2e10 flop (at most 1024 matrices), so that
+every candidate runs in the throughput regime of a large batch.
 """
 from __future__ import annotations
 
@@ -29,6 +30,7 @@ NBS = [32, 64, 128]
 TREES = ["greedy", "flatts", "flattt", "auto"]
 VARIANTS = ["bidiag", "rbidiag"]
 TARGET_FLOPS = 2.0e10
+MIN_COUNT = 256          # enough matrices to occupy every CU, as in a large batch
 MAX_COUNT = 1024
 
 
@@ -41,7 +43,7 @@ def class_sample(ci, ri, seed):
     m_lo, m_hi = M_EDGES[ci], M_EDGES[ci + 1]
     r_lo, r_hi = R_EDGES[ri], R_EDGES[ri + 1]
     shapes, flops = [], 0.0
-    while flops < TARGET_FLOPS and len(shapes) < MAX_COUNT:
+    while (flops < TARGET_FLOPS or len(shapes) < MIN_COUNT) and len(shapes) < MAX_COUNT:
         m = int(rng.integers(m_lo, m_hi))
         n_lo = max(1, (r_lo * m) // 1000 + 1)
         n_hi = max(n_lo, (r_hi * m) // 1000)
@@ -118,9 +120,9 @@ def main():
           "Command: `python -m paper_1611_06892_amd.autotune --out-dir %s` (seed %d)." %
           (args.out_dir, args.seed),
           "Each class is a batch of seeded N(0,1) matrices with (m, n) uniform in the class, "
-          "sized to about %.0e flop (at most %d matrices); time = best of 2 runs after one "
+          "at least %d matrices and about %.0e flop (at most %d); time = best of 2 runs after one "
           "warm-up, HIP events around the batch's launches; GFLOP/s = sum 4n^2(m-n/3) / time." %
-          (TARGET_FLOPS, MAX_COUNT),
+          (MIN_COUNT, TARGET_FLOPS, MAX_COUNT),
           "",
           "| m | 1000 n/m | matrices | best (GFLOP/s) | 2nd | 3rd | worst |",
           "|---|---|---|---|---|---|---|"]

@@ -294,7 +294,12 @@ int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* s
     hipStream_t s = (hipStream_t)stream;
 
     bbk::KArgs a{};
-    a.mats = (const bbk::MatDesc*)((char*)ws + ws_mats_off());
+    if (d0) {
+        a.single = *d0;
+        a.mats = nullptr;
+    } else {
+        a.mats = (const bbk::MatDesc*)((char*)ws + ws_mats_off());
+    }
     a.vt = (double*)vt;
     a.slot_stride = bbk::record_doubles(P->nb);
     char* blob = (char*)P->dblob;
@@ -310,8 +315,7 @@ int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* s
     if (timed && !P->ev0) {
         if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
     }
-    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), d0, s) !=
-        hipSuccess)
+    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), s) != hipSuccess)
         return BB_EHIP;
     if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
     if (a.nunits > 0) {

@@ -86,8 +86,34 @@ struct TileView {
     }
 };
 
+// Descriptor of the task's matrix.  A single-matrix launch carries it in the
+// kernel arguments.  A batched launch reads it from the workspace, where an
+// earlier kernel of the stream wrote it: the loads are agent-scope atomics,
+// so no cache level can serve a value left there by an earlier launch that
+// used the same workspace.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ MatDesc mat_desc(const KArgs& a, int mat) {
+    if (a.mats == nullptr) return a.single;
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(a.mats + mat);
+    uint64_t f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        f[k] = uniform64(__hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    MatDesc d;
+    d.A = reinterpret_cast<double*>(f[0]);
+    d.lda = (int64_t)f[1];
+    d.m = (int64_t)f[2];
+    d.n = (int64_t)f[3];
+    return d;
+}
+
 __device__ __forceinline__ TileView view(const KArgs& a, const DevTask& tk, int pr, int pc, int nb) {
-    const MatDesc d = a.mats[tk.mat];
+    const MatDesc d = mat_desc(a, tk.mat);
     const int trans = tk.trans & 1;
     TileView t;
     t.base = d.A + (int64_t)pr * nb + (int64_t)pc * nb * d.lda;
@@ -766,21 +792,17 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
     }
 }
 
-__global__ void init_kernel(int32_t* deps, const int32_t* ndeps, int32_t ntasks, int32_t* ctrl,
-                            MatDesc d0, MatDesc* mats, int write_d0) {
+__global__ void init_kernel(int32_t* deps, const int32_t* ndeps, int32_t ntasks, int32_t* ctrl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < CTRL_WORDS) ctrl[i] = 0;
-    if (write_d0 && i == 0) mats[0] = d0;
     for (int t = i; t < ntasks; t += gridDim.x * blockDim.x) deps[t] = ndeps[t];
 }
 
-hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, const MatDesc* d0,
-                       hipStream_t s) {
+hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s) {
     int blocks = (ntasks + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, a.deps, ndeps_init, ntasks, a.ctrl,
-                       d0 ? *d0 : MatDesc{}, const_cast<MatDesc*>(a.mats), d0 ? 1 : 0);
+    hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, a.deps, ndeps_init, ntasks, a.ctrl);
     return hipGetLastError();
 }
 

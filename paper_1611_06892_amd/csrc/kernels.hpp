@@ -22,7 +22,8 @@ struct MatDesc {
 enum : int { CTRL_TICKET = 0, CTRL_ERROR = 1, CTRL_DONE = 2, CTRL_WORDS = 64 };
 
 struct KArgs {
-    const MatDesc* mats;     // matrices of the launch (in the workspace)
+    MatDesc single;          // the matrix of a single-matrix launch (mats == NULL)
+    const MatDesc* mats;     // batched launch: the matrices' descriptors (in the workspace)
     double* vt;              // V/T records
     int64_t slot_stride;     // doubles per record (record_doubles(nb))
     const DevTask* tasks;
@@ -42,10 +43,8 @@ inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
 inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
-// Resets the scheduler words and dependency counters; with d0 != NULL also
-// writes *d0 as the launch's only matrix descriptor (a.mats[0]).
-hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, const MatDesc* d0,
-                       hipStream_t s);
+// Resets the scheduler words and dependency counters.
+hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
 // Fills mats[i] = {A[gidx[i]], lda[gidx[i]], dims[2i], dims[2i+1]} for the
 // nmats matrices of one group of a batched launch (A, lda: the caller's device
 // arrays; gidx, dims: the plan's device copy).

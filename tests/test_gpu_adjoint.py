@@ -41,7 +41,7 @@ def forward(bb, A, nb, tree, variant):
 
 
 CASES = [
-    (96, 64, 16, "greedy", "bidiag"),
+    (160, 96, 32, "greedy", "bidiag"),
     (200, 130, 32, "flatts", "rbidiag"),     # ragged
     (256, 256, 64, "auto", "bidiag"),
     (640, 256, 128, "greedy", "rbidiag"),
@@ -128,3 +128,17 @@ def test_adjoint_full_size(bb):
         an = float(np.sum(Ag * E))
         print("fd", fd, "adjoint", an, "|grad|", nAg, flush=True)
         assert abs(fd - an) <= 1e-5 * nAg
+
+
+def test_band_does_not_modify_its_input(bb):
+    """Regression: a column-major FP64 CUDA input (Fortran strides) must be
+    copied, not reduced in place."""
+    A0 = workloads.gaussian(300, 192, seed=3)
+    A = torch.as_tensor(A0).cuda()
+    assert A.stride() == (1, 300)
+    B, _, _ = bb.band(A, 64, "greedy", "rbidiag")
+    torch.cuda.synchronize()
+    assert np.array_equal(A.cpu().numpy(), A0)
+    Ag = A.clone().requires_grad_(True)
+    bb.band_autograd(Ag, 64, "greedy", "rbidiag")
+    assert np.array_equal(Ag.detach().cpu().numpy(), A0)
