@@ -70,8 +70,10 @@ enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2 };
  * the mixed forms are an extension.) */
 enum { BB_F64 = 0, BB_F64_UPD_F32 = 2, BB_F64_UPD_SPLIT32 = 3 };
 /* Execution of the task graph: one persistent launch whose workgroups take
- * tasks in a precomputed priority order and wait on dependency counters
- * (default), or one launch per topological level of the graph. */
+ * work units in a precomputed priority order (a list-scheduling simulation
+ * on the GPU's workgroups, by bottom level in the task graph, R-BiDiag's
+ * second phase first) and wait on dependency counters (default), or one
+ * launch per topological level of the graph. */
 enum { BB_SCHED_PERSISTENT = 0, BB_SCHED_LEVELS = 1 };
 
 typedef struct {
@@ -86,6 +88,9 @@ typedef struct {
 } bb_opts;
 
 #define BB_FLAG_TIMING 1  /* record HIP events around the main kernel(s) */
+#define BB_FLAG_TRACE  2  /* persistent scheduler: record per-unit timestamps in the
+                             workspace (bb_plan_trace); the workspace grows by
+                             32 bytes per work unit */
 
 typedef struct bb_plan bb_plan;
 
@@ -162,6 +167,16 @@ int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, in
 /* Workspace sizes for bidiag_band with the same arguments. */
 int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
              size_t* vt_bytes, size_t* ws_bytes);
+
+/*
+ * bb_plan_trace -- where a BB_FLAG_TRACE plan's execution trace lives in its
+ * workspace: *offset (bytes from ws) of nunits records of 4 int64
+ * {ready-wait start, run start, run end, workgroup}, wall-clock ticks of
+ * *tick_hz, in ticket order; units[2k], units[2k+1] (optional, host, 2 *
+ * nunits int32) receive the (task, column strip) of record k.  Valid after a
+ * bb_execute of the plan with BB_SCHED_PERSISTENT has completed.
+ */
+int bb_plan_trace(bb_plan* plan, size_t* offset, int64_t* nunits, double* tick_hz, int32_t* units);
 
 /*
  * bb_apply_q / bb_apply_p -- apply the orthogonal factors of a finished

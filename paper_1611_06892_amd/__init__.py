@@ -25,6 +25,7 @@ PRECS = {"f64": 0, "f64_upd_f32": 2, "f64_upd_split32": 3}
 SCHEDS = {"persistent": 0, "levels": 1}
 KINDS = ["GEQRT", "TSQRT", "TTQRT", "UNMQR", "TSMQR", "TTMQR"]
 FLAG_TIMING = 1
+FLAG_TRACE = 2
 
 
 class BidiagError(RuntimeError):
@@ -57,7 +58,7 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_tuned_config", "bb_batch_create", "bb_batch_destroy", "bb_batch_workspace",
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
-           "bb_adjoint_workspace"]
+           "bb_adjoint_workspace", "bb_plan_trace"]
 
 
 def lib():
@@ -136,6 +137,8 @@ def lib():
     L.bidiag_band_adjoint.restype = i32
     L.bb_adjoint_workspace.argtypes = [P, szp]
     L.bb_adjoint_workspace.restype = i32
+    L.bb_plan_trace.argtypes = [P, szp, lp, ctypes.POINTER(ctypes.c_double), vp]
+    L.bb_plan_trace.restype = i32
     L.bb_strerror.argtypes = [i32]
     L.bb_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -152,9 +155,9 @@ def _check(rc: int, where: str):
 
 
 def make_opts(workgroups=0, gamma=0.0, auto_a=0, sched="persistent", watchdog_s=0.0,
-              timing=False) -> _Opts:
+              timing=False, trace=False) -> _Opts:
     return _Opts(int(workgroups), float(gamma), int(auto_a), SCHEDS[sched], float(watchdog_s),
-                 FLAG_TIMING if timing else 0)
+                 (FLAG_TIMING if timing else 0) | (FLAG_TRACE if trace else 0))
 
 
 def critical_path(p: int, q: int, tree="greedy", variant="bidiag", auto_a=0, workgroups=256,
@@ -282,6 +285,24 @@ class Plan:
         ms = ctypes.c_double()
         _check(lib().bb_plan_last_kernel_ms(self._h, ctypes.byref(ms)), "bb_plan_last_kernel_ms")
         return ms.value
+
+    def trace(self, ws):
+        """Per-unit records of the last persistent execution (trace=True plans):
+        a dict of numpy arrays task, part, kind, wait, start, end (seconds from
+        the first start) and workgroup."""
+        off, nu, hz = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().bb_plan_trace(self._h, ctypes.byref(off), ctypes.byref(nu), ctypes.byref(hz),
+                                   None), "bb_plan_trace")
+        units = np.zeros(2 * max(nu.value, 1), dtype=np.int32)
+        _check(lib().bb_plan_trace(self._h, None, None, None, units.ctypes.data), "bb_plan_trace")
+        raw = ws[off.value: off.value + 32 * nu.value].view(-1).cpu().numpy().view(np.int64)
+        raw = raw.reshape(nu.value, 4)
+        tasks, _, _ = self.export()
+        t0 = raw[:, 1].min() if nu.value else 0
+        task = units[0:2 * nu.value:2]
+        return {"task": task, "part": units[1:2 * nu.value:2], "kind": tasks[task, 0],
+                "wait": (raw[:, 0] - t0) / hz.value, "start": (raw[:, 1] - t0) / hz.value,
+                "end": (raw[:, 2] - t0) / hz.value, "workgroup": raw[:, 3]}
 
     def adjoint_workspace(self) -> int:
         ws = ctypes.c_size_t()

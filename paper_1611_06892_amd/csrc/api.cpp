@@ -32,7 +32,8 @@ struct bb_plan {
     bb::Graph g;
     int ns = 0;                              // update strip width
     std::vector<int32_t> nparts, ndeps, succ_off, succ_idx;
-    std::vector<int32_t> units_ticket;       // (task, part) pairs, priority order
+    std::vector<int32_t> units_ticket;       // (task, part) pairs, list-scheduling order
+    std::vector<int32_t> units_prio;         // persistent scheduler: (task, part) pairs by priority
     std::vector<int32_t> units_level;        // (task, part) pairs sorted by level
     std::vector<int32_t> level_off;          // units_level offsets per level
     double cp = 0.0, total = 0.0;
@@ -41,6 +42,7 @@ struct bb_plan {
     void* dblob = nullptr;
     size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_ut = 0, off_ul = 0;
     size_t off_gidx = 0, off_dims = 0;
+    size_t off_up = 0;
     int cu_count = 0;
     double wallclock_khz = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -87,8 +89,9 @@ const double kUnit[bb::NKINDS] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0, 6.0, 12.0, 6.0}
 // task with its column strips run side by side).  Unlike Table 1, whose unit
 // is flops, it reflects that a panel is a chain of nb dependent Householder
 // steps while an update is throughput-bound MFMA work (measured on MI355X for
-// nb = 128: panels ~110 us, UNMQR / TSMQR / TTMQR strips ~25 / 36 / 30 us).
-const double kGpuCost[bb::NKINDS] = {11.0, 11.0, 11.0, 2.5, 3.6, 3.0, 2.5, 3.6, 3.0};
+// nb = 128 in a loaded run: panels ~160-175 us, UNMQR / TSMQR / TTMQR strips
+// ~25 / 37 / 36 us).
+const double kGpuCost[bb::NKINDS] = {16.0, 17.0, 17.0, 2.5, 3.7, 3.6, 2.5, 3.7, 3.6};
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -147,6 +150,15 @@ int build_schedule(bb_plan& P) {
         for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) b = std::max(b, blevel[P.succ_idx[s]]);
         blevel[t] = b + kGpuCost[g.tasks[t].kind];
     }
+    // R-BiDiag: the band reduction of R (second phase) is a chain of panels
+    // that occupies few CUs while the QR(p,q) phase is throughput-bound, so
+    // its tasks go first whenever they are ready.
+    std::vector<double> prio(blevel);
+    if (g.phase2_start >= 0) {
+        double bmax = 0.0;
+        for (int t = 0; t < nt; ++t) bmax = std::max(bmax, blevel[t]);
+        for (int t = g.phase2_start; t < nt; ++t) prio[t] += bmax;
+    }
     P.cp = bb::critical_path(g, kUnit);
     P.total = 0.0;
     for (int t = 0; t < nt; ++t) P.total += kUnit[g.tasks[t].kind];
@@ -163,7 +175,7 @@ int build_schedule(bb_plan& P) {
         indeg[t] = (int32_t)g.pred[t].size();
         left[t] = P.nparts[t];
         if (indeg[t] == 0)
-            for (int q = 0; q < P.nparts[t]; ++q) ready.emplace(-blevel[t], t, q);
+            for (int q = 0; q < P.nparts[t]; ++q) ready.emplace(-prio[t], t, q);
     }
     P.units_ticket.clear();
     double now = 0.0;
@@ -188,10 +200,14 @@ int build_schedule(bb_plan& P) {
             for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) {
                 int v = P.succ_idx[s];
                 if (--indeg[v] == 0)
-                    for (int q = 0; q < P.nparts[v]; ++q) ready.emplace(-blevel[v], v, q);
+                    for (int q = 0; q < P.nparts[v]; ++q) ready.emplace(-prio[v], v, q);
             }
         }
     }
+
+    // The persistent scheduler claims units in this simulated start order
+    // (topological: a unit starts after its predecessors finished).
+    P.units_prio = P.units_ticket;
 
     // Levels: longest path, in tasks, from a source.
     std::vector<int32_t> level(nt, 0);
@@ -223,8 +239,13 @@ size_t ws_mats_off() { return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256); 
 size_t ws_deps_off(const bb_plan& P) {
     return ws_mats_off() + round_up(sizeof(bbk::MatDesc) * (size_t)P.nmats, 256);
 }
-size_t ws_bytes_of(const bb_plan& P) {
+size_t ws_trace_off(const bb_plan& P) {
     return ws_deps_off(P) + round_up(sizeof(int32_t) * P.g.tasks.size(), 256);
+}
+size_t ws_bytes_of(const bb_plan& P) {
+    size_t b = ws_trace_off(P);
+    if (P.opts.flags & BB_FLAG_TRACE) b += round_up(4 * sizeof(int64_t) * (P.units_ticket.size() / 2), 256);
+    return b;
 }
 
 size_t vt_bytes_of(const bb_plan& P) {
@@ -261,6 +282,7 @@ int ensure_device(bb_plan& P) {
     P.off_succ_idx = off; off = round_up(off + std::max<size_t>(1, P.succ_idx.size()) * 4, 256);
     P.off_ut = off; off = round_up(off + P.units_ticket.size() * 4, 256);
     P.off_ul = off; off = round_up(off + P.units_level.size() * 4, 256);
+    P.off_up = off; off = round_up(off + P.units_prio.size() * 4, 256);
     P.off_gidx = off; off = round_up(off + P.gidx.size() * 8, 256);
     P.off_dims = off; off = round_up(off + P.dims.size() * 8, 256);
     std::vector<char> host(off, 0);
@@ -270,6 +292,10 @@ int ensure_device(bb_plan& P) {
     if (!P.succ_idx.empty()) std::memcpy(host.data() + P.off_succ_idx, P.succ_idx.data(), P.succ_idx.size() * 4);
     std::memcpy(host.data() + P.off_ut, P.units_ticket.data(), P.units_ticket.size() * 4);
     std::memcpy(host.data() + P.off_ul, P.units_level.data(), P.units_level.size() * 4);
+    auto put = [&](size_t o, const std::vector<int32_t>& v) {
+        if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * 4);
+    };
+    put(P.off_up, P.units_prio);
     if (!P.gidx.empty()) std::memcpy(host.data() + P.off_gidx, P.gidx.data(), P.gidx.size() * 8);
     if (!P.dims.empty()) std::memcpy(host.data() + P.off_dims, P.dims.data(), P.dims.size() * 8);
     void* d = nullptr;
@@ -310,22 +336,23 @@ int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* s
     a.ctrl = (int32_t*)ws;
     a.deps = (int32_t*)((char*)ws + ws_deps_off(*P));
     a.watchdog_ticks = (int64_t)(P->opts.watchdog_s * P->wallclock_khz * 1000.0);
+    a.trace = (P->opts.flags & BB_FLAG_TRACE) ? (int64_t*)((char*)ws + ws_trace_off(*P)) : nullptr;
 
     const bool timed = (P->opts.flags & BB_FLAG_TIMING) != 0;
     if (timed && !P->ev0) {
         if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
     }
+    const bool persistent = P->opts.sched == BB_SCHED_PERSISTENT;
+    a.units = (const int2*)(blob + (persistent ? P->off_up : P->off_ul));
     if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), s) != hipSuccess)
         return BB_EHIP;
     if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
     if (a.nunits > 0) {
-        if (P->opts.sched == BB_SCHED_PERSISTENT) {
-            a.units = (const int2*)(blob + P->off_ut);
+        if (persistent) {
             int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
             wg = std::max(1, std::min(wg, a.nunits));
             if (bbk::launch_persistent(P->nb, P->prec, a, wg, s) != hipSuccess) return BB_EHIP;
         } else {
-            a.units = (const int2*)(blob + P->off_ul);
             for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
                 int32_t b = P->level_off[l], e = P->level_off[l + 1];
                 if (bbk::launch_level(P->nb, P->prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
@@ -709,6 +736,26 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     if (rc != BB_OK) return rc;
     const bbk::MatDesc dQ{(double*)Abar, ldabar, P->m, n};
     return launch_plan(*Qp, &dQ, const_cast<void*>(vt), w + L.apply, stream);
+}
+
+int bb_plan_trace(bb_plan* P, size_t* offset, int64_t* nunits, double* tick_hz, int32_t* units) {
+    if (!P) return -1;
+    if (!(P->opts.flags & BB_FLAG_TRACE)) return BB_ENOTSUP;
+    if (offset) *offset = ws_trace_off(*P);
+    if (nunits) *nunits = (int64_t)(P->units_ticket.size() / 2);
+    if (tick_hz) {
+        if (P->wallclock_khz <= 0.0) {
+            int dev = 0, khz = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+                khz = 100000;
+            *tick_hz = 1000.0 * khz;
+        } else {
+            *tick_hz = 1000.0 * P->wallclock_khz;
+        }
+    }
+    if (units) std::copy(P->units_prio.begin(), P->units_prio.end(), units);
+    return BB_OK;
 }
 
 int bb_plan_last_kernel_ms(bb_plan* P, double* ms) {

@@ -726,67 +726,96 @@ __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
     run_unit<NB, false, PREC>(a, u.x, u.y, lds);
 }
 
-// Persistent scheduler.  Each workgroup repeatedly takes the next ticket (a
-// unit in a precomputed topological priority order), waits until the unit's
-// task has no unfinished predecessor parts, runs it and decrements the
-// counters of the task's successors.  Tickets are only taken by running
-// workgroups and every predecessor of a ticket has a smaller ticket, so the
-// lowest unfinished ticket can always proceed: no deadlock for any grid size.
-// A wall-clock watchdog bounds every wait; on expiry (or when another
-// workgroup reports an error) the workgroup records the error and exits.
+// Persistent scheduler.  The work units are listed in one priority order:
+// the start order of a list-scheduling simulation of the task graph on the
+// GPU's workgroups (most urgent ready unit first), which is topological (a
+// unit's predecessors all come earlier).  Each workgroup takes the next
+// position of that order (one atomic add on the ticket counter) and waits
+// until the unit's task has no unfinished predecessor unit.  Tickets go only
+// to running workgroups and every predecessor holds an earlier ticket, so the
+// earliest unfinished ticket can always proceed: no deadlock for any grid
+// size.  A wall-clock watchdog bounds every wait (error 3 after watchdog_ticks),
+// and an error reported by any workgroup stops all of them.
+__device__ __forceinline__ int aload(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of wave 0; returns the same value in every lane:
+// a ticket (priority position) whose unit is ready, or -1 to stop.
+__device__ __forceinline__ int next_unit(const KArgs& a, int lane) {
+    int u = 0;
+    if (lane == 0)
+        u = __hip_atomic_fetch_add(&a.ctrl[CTRL_HEAD], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    u = __builtin_amdgcn_readfirstlane(u);
+    if (u >= a.nunits) return -1;
+    const int task = __builtin_amdgcn_readfirstlane(a.units[u].x);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        int d = 0, err = 0;
+        if (lane == 0) {
+            d = aload(&a.deps[task]);
+            if (d > 0) err = aload(&a.ctrl[CTRL_ERROR]);
+        }
+        d = __builtin_amdgcn_readfirstlane(d);
+        if (d <= 0) return u;
+        if (__builtin_amdgcn_readfirstlane(err) != 0) return -1;
+        if ((int64_t)(wall_clock64() - t0) > a.watchdog_ticks) {
+            if (lane == 0) __hip_atomic_store(&a.ctrl[CTRL_ERROR], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Thread 0, after the unit's outputs are complete: count down the
+// successors' dependency counters, then count the unit as done.
+__device__ __forceinline__ void complete_unit(const KArgs& a, int task) {
+    const int s0 = a.succ_off[task], s1 = a.succ_off[task + 1];
+    for (int e = s0; e < s1; ++e)
+        __hip_atomic_fetch_add(&a.deps[a.succ_idx[e]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&a.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
     __shared__ double lds[Shape<NB>::LDS];
-    __shared__ int s_unit, s_stop;
+    __shared__ int s_unit;
+    __shared__ uint64_t s_wait;
     const int tid = threadIdx.x;
     for (;;) {
-        if (tid == 0) {
-            s_unit = __hip_atomic_fetch_add(&a.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-            s_stop = 0;
-        }
-        __syncthreads();
-        // The ticket is the same for every thread; readfirstlane makes that
-        // visible to the compiler so the loop exits stay uniform.  (With
-        // exits it must treat as divergent, the loop is restructured so that
-        // lanes other than 0 re-enter the top barrier before lane 0 fetched
-        // the next ticket.)
-        const int u = __builtin_amdgcn_readfirstlane(s_unit);
-        if (u >= a.nunits) break;
-        const int2 un0 = a.units[u];
-        const int2 un = make_int2(__builtin_amdgcn_readfirstlane(un0.x),
-                                  __builtin_amdgcn_readfirstlane(un0.y));
-        if (tid == 0) {
-            const uint64_t t0 = wall_clock64();
-            for (;;) {
-                int d = __hip_atomic_load(&a.deps[un.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (d <= 0) break;
-                if (__hip_atomic_load(&a.ctrl[CTRL_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    s_stop = 1;
-                    break;
-                }
-                if ((int64_t)(wall_clock64() - t0) > a.watchdog_ticks) {
-                    __hip_atomic_store(&a.ctrl[CTRL_ERROR], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_stop = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+        if (tid < 64) {
+            const uint64_t tw = wall_clock64();
+            const int unit = next_unit(a, tid);
+            if (tid == 0) {
+                s_unit = unit;
+                s_wait = tw;
             }
         }
         __syncthreads();
-        if (__builtin_amdgcn_readfirstlane(s_stop)) break;
+        // Uniform in the workgroup; readfirstlane lets the compiler see that,
+        // which keeps the loop's exits uniform.
+        const int u = __builtin_amdgcn_readfirstlane(s_unit);
+        if (u < 0) break;
+        const int2 un0 = a.units[u];
+        const int2 un = make_int2(__builtin_amdgcn_readfirstlane(un0.x),
+                                  __builtin_amdgcn_readfirstlane(un0.y));
         // Acquire: drop stale lines of the inputs from this CU's caches and
         // this XCD's L2.  Release: the unit wrote its outputs with agent-scope
         // stores, so waiting for them to complete publishes them to every XCD.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint64_t t_run = a.trace != nullptr && tid == 0 ? wall_clock64() : 0;
         run_unit<NB, true, PREC>(a, un.x, un.y, lds);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
-            const int s0 = a.succ_off[un.x], s1 = a.succ_off[un.x + 1];
-            for (int s = s0; s < s1; ++s)
-                __hip_atomic_fetch_add(&a.deps[a.succ_idx[s]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&a.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.trace != nullptr) {
+                int64_t* tr = a.trace + 4 * (int64_t)u;
+                tr[0] = (int64_t)s_wait;
+                tr[1] = (int64_t)t_run;
+                tr[2] = (int64_t)wall_clock64();
+                tr[3] = blockIdx.x;
+            }
+            complete_unit(a, un.x);
         }
         __syncthreads();
     }

@@ -18,8 +18,9 @@ struct MatDesc {
     int64_t lda, m, n;
 };
 
-// Scheduler control words at the start of the workspace.
-enum : int { CTRL_TICKET = 0, CTRL_ERROR = 1, CTRL_DONE = 2, CTRL_WORDS = 64 };
+// Scheduler control words at the start of the workspace: error flag,
+// completed-unit count and the ticket counter, each in its own 64-byte line.
+enum : int { CTRL_ERROR = 1, CTRL_DONE = 16, CTRL_HEAD = 32, CTRL_WORDS = 64 };
 
 struct KArgs {
     MatDesc single;          // the matrix of a single-matrix launch (mats == NULL)
@@ -27,13 +28,15 @@ struct KArgs {
     double* vt;              // V/T records
     int64_t slot_stride;     // doubles per record (record_doubles(nb))
     const DevTask* tasks;
-    const int2* units;       // (task, part) in execution order
+    const int2* units;       // levels: (task, part) by level; persistent: (task, part) by priority
     int32_t nunits;
     const int32_t* succ_off; // CSR successors
     const int32_t* succ_idx;
     int32_t* deps;           // live dependency counters (persistent mode)
     int32_t* ctrl;           // CTRL_* words
     int64_t watchdog_ticks;  // wall-clock ticks without progress before giving up
+    int64_t* trace;          // NULL, or 4 int64 per unit (persistent mode):
+                             // {ready-wait start, run start, run end, workgroup}
 };
 
 // Update strip width (columns of the logical C tile per work unit).
@@ -43,7 +46,7 @@ inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
 inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
-// Resets the scheduler words and dependency counters.
+// Resets the scheduler words and the dependency counters.
 hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks, hipStream_t s);
 // Fills mats[i] = {A[gidx[i]], lda[gidx[i]], dims[2i], dims[2i+1]} for the
 // nmats matrices of one group of a batched launch (A, lda: the caller's device

@@ -209,6 +209,7 @@ std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g) {
             for (int k = 0; k < q; ++k) b.run_step(0, k, k, p, k + 1, q);
         }
         if (opt.variant == QRONLY) return std::string();
+        g.phase2_start = (int32_t)g.tasks.size();
         for (int k = 0; k < q; ++k) {
             if (k > 0) b.run_step(0, k, k, q, k + 1, q);       // QR(k) on the top q x q
             if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, q);  // LQ(k)

@@ -63,6 +63,7 @@ struct Graph {
     int32_t nslots = 0;                      // V/T slots (one per panel task)
     int32_t nsteps = 0;
     std::vector<int32_t> auto_a_used;        // per step (Auto), for inspection
+    int32_t phase2_start = -1;               // R-BiDiag: first task of the band reduction of R
 };
 
 // Build the task graph.  Returns an empty string on success, else a message.
