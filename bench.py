@@ -56,6 +56,30 @@ def time_plan(bb, torch, plan, S0, m, steps, warmup):
     return (t1 - t0) * 1e3 / steps, kms, S
 
 
+def measured_traffic(args, m, n, nb):
+    """HBM bytes per launch of the persistent kernel from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), for
+    the configuration it was measured on and only while the kernel source is
+    the one measured; else None."""
+    import hashlib
+    if (args.workload, m, n, nb, args.variant, args.tree, args.prec, args.sched) != \
+            ("tall_graded", 32768, 2048, 128, "rbidiag", "greedy", "f64", "persistent"):
+        return None
+    here = os.path.dirname(os.path.abspath(__file__))
+    summary = os.path.join(here, "profiles",
+                           "persistent_kernel_tall_graded_32768x2048_nb128_rbidiag_greedy.md")
+    src = os.path.join(here, "paper_1611_06892_amd", "csrc", "kernels.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(summary).read().splitlines()
+                      if line.startswith(("traffic_bytes: ", "kernel_source_sha256_prefix: ")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256_prefix") != sha:
+        return None
+    return float(fields["traffic_bytes"])
+
+
 def cpu_baseline(workloads):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -310,7 +334,8 @@ def main():
     achieved = algo / (kern_ms * 1e-3) / 1e12
     peak = FP64_PEAK_TFLOPS if args.prec == "f64" else FP32_PEAK_TFLOPS
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(args, m, n, nb),
                 "kernel": "persistent_kernel<%d, %d>" % (nb, bb.PRECS[args.prec]),
                 "kernel_ms": round(kern_ms, 3),
                 "algorithmic_flops": algo}
