@@ -62,10 +62,17 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // stores, which are made coherent across the L2s of all XCDs as they
 // complete; the persistent scheduler uses them so that finishing a task needs
 // only a wait for its stores instead of an L2 write-back.
+// Matrix tiles and records are global memory.  Accessing them through
+// global-address-space pointers (not generic ones) keeps them off the LDS
+// counter, so LDS waits in the products do not also wait for global loads.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble* gptr(double* p) { return (gdouble*)p; }
+
 template <bool CO>
 __device__ __forceinline__ void gstore(double* p, double v) {
-    if (CO) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else *p = v;
+    gdouble* q = gptr(p);
+    if (CO) __hip_atomic_store(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *q = v;
 }
 
 // A tile seen in the logical frame.  vr/vc: logical rows/columns that exist in
@@ -78,7 +85,7 @@ struct TileView {
         return trans ? base + c + (int64_t)r * ld : base + r + (int64_t)c * ld;
     }
     __device__ __forceinline__ double get(int r, int c) const {
-        return (r < vr && c < vc) ? *ptr(r, c) : 0.0;
+        return (r < vr && c < vc) ? *gptr(ptr(r, c)) : 0.0;
     }
     template <bool CO>
     __device__ __forceinline__ void put(int r, int c, double v) const {
