@@ -96,7 +96,9 @@ __global__ __launch_bounds__(256) void adj_ew(AArgs a, const AOp* ops, int32_t o
         default: break;
         }
         double v = 0.0;
-        if (keep) {
+        if (op.flag == AM_IDENT) {
+            v = r == c ? 1.0 : 0.0;
+        } else if (keep) {
             if (op.alpha != 0.0) v += op.alpha * *at(a, op.X, r, c);
             if (op.b2 != 0.0) v += op.b2 * *at(a, op.X, c, r);
         }

@@ -25,7 +25,7 @@ namespace bbk {
 
 // Buffers the operations refer to (by index).
 enum : int32_t { AB_B = 0, AB_W = 1, AB_G = 2, AB_OM = 3, AB_PS = 4, AB_TMP = 5, AB_GT = 6, AB_ABAR = 7,
-                 AB_NBUF = 8 };
+                 AB_INV = 8, AB_NBUF = 9 };
 
 // View of a buffer: element (r, c) is buf[(r0 + r) + (c0 + c) ld] when
 // trans = 0 and buf[(r0 + c) + (c0 + r) ld] when trans = 1.
@@ -36,7 +36,8 @@ struct AView {
 
 enum : int32_t { AOP_GEMM = 0, AOP_TRSM = 1, AOP_EW = 2 };
 // Elementwise masks (r, c of the destination).
-enum : int32_t { AM_ALL = 0, AM_SUPPER = 1, AM_SLOWER = 2, AM_UPPER = 3, AM_LOWER = 4 };
+// AM_IDENT writes the identity (X is not read).
+enum : int32_t { AM_ALL = 0, AM_SUPPER = 1, AM_SLOWER = 2, AM_UPPER = 3, AM_LOWER = 4, AM_IDENT = 5 };
 
 // GEMM: D = beta D + alpha X Y (M x N, inner K); beta = 0 does not read D.
 // TRSM: D = alpha X^-1 D with X M x M triangular (flag 1: upper, 0: lower),

@@ -86,6 +86,21 @@ void build_adjoint_ops(int64_t m, int64_t n, int nb, AdjointOps& out) {
     auto Bv = [&](int i, int j) { return b.blk(AB_B, i, j); };
     const int64_t npad = (int64_t)q * nb;
 
+    // Inverses of the triangular blocks, once: INV block row k holds
+    // B_kk^-1 (upper) in columns [0, nb) and, for k < q-1, the inverse of the
+    // leading r x r (lower) part of B_k,k+1 in columns [nb, 2nb).  Every
+    // triangular solve of the sweep is then a block product.
+    auto Ikk = [&](int k) { return b.v(AB_INV, (int64_t)k * nb, 0); };
+    auto I1 = [&](int k) { return b.v(AB_INV, (int64_t)k * nb, NB); };
+    for (int k = 0; k < q; ++k) {
+        b.ew(Ikk(k), AM_IDENT, 0.0, Ikk(k), 0.0, b.sz(k), b.sz(k), 0.0);
+        if (k + 1 < q) b.ew(I1(k), AM_IDENT, 0.0, I1(k), 0.0, b.sz(k + 1), b.sz(k + 1), 0.0);
+    }
+    for (int k = 0; k < q; ++k) {
+        b.trsm(Ikk(k), Bv(k, k), 1, b.sz(k), b.sz(k));
+        if (k + 1 < q) b.trsm(I1(k), Bv(k, k + 1), 0, b.sz(k + 1), b.sz(k + 1));
+    }
+
     // bars start at zero
     b.ew(b.v(AB_G, 0, 0), AM_ALL, 0.0, b.v(AB_G, 0, 0), 0.0, (int)n, (int)n, 0.0);
     b.ew(b.v(AB_OM, 0, 0), AM_ALL, 0.0, b.v(AB_OM, 0, 0), 0.0, (int)npad, (int)npad, 0.0);
@@ -100,8 +115,7 @@ void build_adjoint_ops(int64_t m, int64_t n, int nb, AdjointOps& out) {
             b.ew(T1, AM_ALL, 1.0, b.blk(AB_PS, k + 1, k + 1), 0.0, nk1, nk1, 0.0);
             b.gemm(T1, 1.0, Builder::T(Bv(k, k + 1)), Z(k), nk1, nk1, nk);           // Pdbar
             b.ew(T2, AM_SUPPER, -1.0, T1, 1.0, nk1, nk1, 0.0);                         // Ybar
-            b.trsm(T2, Builder::T(Bv(k, k + 1)), 1, r, r);                             // B1[:r,:r]^-T Ybar
-            b.ew(Z(k), AM_ALL, 1.0, T2, 0.0, r, r, 1.0);
+            b.gemm(Z(k), 1.0, Builder::T(I1(k)), T2, r, r, r);                        // += B1[:r,:r]^-T Ybar
             b.ew(b.blk(AB_G, k, k + 1), AM_ALL, 1.0, Z(k), 0.0, nk, nk1, 1.0);
             b.ombar(k, k, -1.0, Z(k), Builder::T(Bv(k, k + 1)), nk, nk, nk1);
             b.ombar(k, k + 1, -1.0, Z(k), Builder::T(Bv(k + 1, k + 1)), nk, nk1, nk1);
@@ -109,8 +123,7 @@ void build_adjoint_ops(int64_t m, int64_t n, int nb, AdjointOps& out) {
             // ---- row step k, blocks (k, j), j > k+1 (block k+1 is full) ----
             for (int j = k + 2; j < q; ++j) {
                 const int nj = b.sz(j);
-                b.ew(Z(j), AM_ALL, -1.0, b.blk(AB_PS, k + 1, j), 0.0, nb, nj, 0.0);
-                b.trsm(Z(j), Builder::T(Bv(k, k + 1)), 1, nb, nj);
+                b.gemm(Z(j), -1.0, Builder::T(I1(k)), b.blk(AB_PS, k + 1, j), nb, nj, nb, 0.0);
                 b.ew(b.blk(AB_G, k, j), AM_ALL, 1.0, Z(j), 0.0, nk, nj, 1.0);
                 b.ombar(k, j - 1, -1.0, Z(j), Builder::T(Bv(j - 1, j)), nk, b.sz(j - 1), nj);
                 b.ombar(k, j, -1.0, Z(j), Builder::T(Bv(j, j)), nk, nj, nj);
@@ -122,8 +135,7 @@ void build_adjoint_ops(int64_t m, int64_t n, int nb, AdjointOps& out) {
         b.ew(T1, AM_ALL, 1.0, b.blk(AB_OM, k, k), 0.0, nk, nk, 0.0);
         b.gemm(T1, -1.0, Z(k), Builder::T(Bv(k, k)), nk, nk, nk);                      // Okbar
         b.ew(T2, AM_SLOWER, 1.0, T1, -1.0, nk, nk, 0.0);                               // Ybar
-        b.trsm(Builder::T(T2), Bv(k, k), 1, nk, nk);                                   // Ybar B_kk^-T
-        b.ew(Z(k), AM_ALL, 1.0, T2, 0.0, nk, nk, 1.0);
+        b.gemm(Z(k), 1.0, T2, Builder::T(Ikk(k)), nk, nk, nk);                        // += Ybar B_kk^-T
         b.ew(b.blk(AB_G, k, k), AM_ALL, 1.0, Z(k), 0.0, nk, nk, 1.0);
         if (k > 0) b.ombar(k, k - 1, -1.0, Z(k), Builder::T(Bv(k - 1, k)), nk, b.sz(k - 1), nk);
         b.psbar(k, k, 1.0, Builder::T(Bv(k, k)), Z(k), nk, nk, nk);
@@ -131,8 +143,7 @@ void build_adjoint_ops(int64_t m, int64_t n, int nb, AdjointOps& out) {
         // ---- column step k, blocks (i, k), i > k ----
         for (int i = k + 1; i < q; ++i) {
             const int ni = b.sz(i);
-            b.ew(Z(i), AM_ALL, 1.0, b.blk(AB_OM, i, k), 0.0, ni, nk, 0.0);
-            b.trsm(Builder::T(Z(i)), Bv(k, k), 1, nk, ni);                             // Ombar B_kk^-T
+            b.gemm(Z(i), 1.0, b.blk(AB_OM, i, k), Builder::T(Ikk(k)), ni, nk, nk, 0.0);  // Ombar B_kk^-T
             b.ew(b.blk(AB_G, i, k), AM_ALL, 1.0, Z(i), 0.0, ni, nk, 1.0);
             if (k > 0) b.ombar(i, k - 1, -1.0, Z(i), Builder::T(Bv(k - 1, k)), ni, b.sz(k - 1), nk);
             b.psbar(i, k, 1.0, Builder::T(Bv(i, i)), Z(i), ni, nk, ni);

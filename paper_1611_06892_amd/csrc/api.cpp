@@ -632,7 +632,7 @@ namespace {
 // Workspace of the adjoint: G, G^T (n x n), the Omega and Psi bar grids
 // (npad x npad), scratch (npad x 3nb), then the apply plans' state.
 struct AdjLayout {
-    size_t g, gt, om, ps, tmp, apply, total;
+    size_t g, gt, om, ps, tmp, inv, apply, total;
 };
 
 int adjoint_layout(bb_plan* P, AdjLayout& L) {
@@ -649,6 +649,7 @@ int adjoint_layout(bb_plan* P, AdjLayout& L) {
     L.om = off; off = round_up(off + sizeof(double) * npad * npad, 256);
     L.ps = off; off = round_up(off + sizeof(double) * npad * npad, 256);
     L.tmp = off; off = round_up(off + sizeof(double) * npad * 3 * nb, 256);
+    L.inv = off; off = round_up(off + sizeof(double) * npad * 2 * nb, 256);
     L.apply = off; off += std::max(ws_bytes_of(*Qp), ws_bytes_of(*Pp));
     L.total = off;
     return BB_OK;
@@ -714,6 +715,7 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     a.buf[bbk::AB_PS] = {(double*)(w + L.ps), npad};
     a.buf[bbk::AB_TMP] = {(double*)(w + L.tmp), npad};
     a.buf[bbk::AB_ABAR] = {(double*)Abar, ldabar};
+    a.buf[bbk::AB_INV] = {(double*)(w + L.inv), npad};
     const bbk::AOp* dops = (const bbk::AOp*)P->adj_dev;
     auto run_stages = [&](int32_t s0, int32_t s1) -> int {
         for (int32_t st = s0; st < s1; ++st) {
