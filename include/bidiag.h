@@ -121,7 +121,7 @@ void bb_plan_destroy(bb_plan* plan);
 /*
  * Bytes of device memory the caller must provide to bb_execute:
  *   vt_bytes : reflector records, one per panel task, FP64 column-major:
- *              V (nb x nb), V^T (nb x nb), then nb/16 blocks T_b^T (16 x 16),
+ *              V (nb x nb), then nb/16 blocks T_b^T (16 x 16),
  *              where the panel's transformation is Q = Q_0 Q_1 ... with
  *              Q_b = I - V_b T_b V_b^T, V_b = columns 16b..16b+15 of V and T_b
  *              upper triangular (compact WY form blocked by 16 columns).

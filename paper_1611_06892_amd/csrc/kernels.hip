@@ -180,7 +180,7 @@ struct Rec {
     __amdgpu_buffer_rsrc_t rsrc;
     __device__ __forceinline__ Rec(const double* base, int nb) {
         rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0,
-                                                 (int)(8 * (2 * nb * nb + 16 * nb)), 0x00020000);
+                                                 (int)(8 * (nb * nb + 16 * nb)), 0x00020000);
     }
     __device__ __forceinline__ double ld(int voff, int soff) const {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0));
@@ -229,9 +229,9 @@ __device__ __forceinline__ double sum16(double v) {
 //  2. trailing: Q_b^T is applied to the column tiles right of the block with
 //     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W).
 //     Column tile J lives in registers of wave J % 4 for the whole kernel.
-// Record (FP64): V (nb x nb, column-major), V^T (column-major), then the
-// nb/16 blocks T_b^T (16 x 16 column-major) -- the same blocked compact-WY
-// form the update kernels apply.
+// Record (FP64): V (nb x nb, column-major), then the nb/16 blocks T_b^T
+// (16 x 16 column-major) -- the same blocked compact-WY form the update
+// kernels apply.
 // ---------------------------------------------------------------------------
 template <int NB, int KIND, bool CO>
 __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds) {
@@ -253,8 +253,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
     double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
     double* gV = rec;
-    double* gVt = rec + NB * NB;
-    double* gTt = rec + 2 * NB * NB;
+    double* gTt = rec + NB * NB;
 
     d4 xt[OWN][MT];
 #pragma unroll
@@ -303,10 +302,15 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 al = sum16(al);
                 double tau = 0.0, beta = al, scale = 0.0;
                 if (ss != 0.0) {
+                    // tau = (beta - al) / beta and scale = 1 / (al - beta)
+                    // from one division: with d = al - beta,
+                    // 1 / (beta d) gives tau = -d^2 / (beta d) and scale = beta / (beta d).
                     const double nrm = sqrt(fma(al, al, ss));
                     beta = al >= 0.0 ? -nrm : nrm;
-                    tau = (beta - al) / beta;
-                    scale = 1.0 / (al - beta);
+                    const double d = al - beta;
+                    const double inv = 1.0 / (beta * d);
+                    tau = -(d * d) * inv;
+                    scale = beta * inv;
                 }
 #pragma unroll
                 for (int s = 0; s < SR; ++s) {
@@ -330,12 +334,13 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             const double tc = taus[c];
             if (lj != c) {
                 if (tc != 0.0) {
-                    double vv[SR], d = 0.0;
+                    double vv[SR], dp[2] = {0.0, 0.0};
 #pragma unroll
                     for (int s = 0; s < SR; ++s) {
                         vv[s] = vb[lq + 16 * s];
-                        d = fma(vv[s], x[s], d);
+                        dp[s & 1] = fma(vv[s], x[s], dp[s & 1]);
                     }
+                    double d = dp[0] + dp[1];
                     if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
                     d = sum16(d);
                     if (lj > c) {
@@ -382,7 +387,6 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 else vv = row > col ? x[s] : (row == col ? 1.0 : 0.0);
                 Lf[row + lj * LDL] = vv;
                 gstore<CO>(gV + row + (int64_t)col * NB, vv);
-                gstore<CO>(gVt + col + (int64_t)row * NB, vv);
                 TX.put<CO>(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
             }
             if (PAIR) T1.put<CO>(16 * b + lq, 16 * b + lj, r1);
@@ -460,7 +464,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     auto fetch = [&](int b, double (&pre)[PRE]) {
 #pragma unroll
         for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
-        pre[PRE - 1] = rec.ld(8 * tid, 8 * (2 * NB * NB + 256 * b));
+        pre[PRE - 1] = rec.ld(8 * tid, 8 * (NB * NB + 256 * b));
     };
     auto stage = [&](int buffer, const double (&pre)[PRE]) {
         double* buf = lds + buffer * BUF;
@@ -596,7 +600,7 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
     auto fetch = [&](int b, double (&pre)[PRE]) {
 #pragma unroll
         for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
-        pre[PRE - 1] = rec.ld(8 * tid, 8 * (2 * NB * NB + 256 * b));
+        pre[PRE - 1] = rec.ld(8 * tid, 8 * (NB * NB + 256 * b));
     };
     auto stage = [&](int b, const double (&pre)[PRE]) {
         float* hi = fl + (b & 1) * BUF;

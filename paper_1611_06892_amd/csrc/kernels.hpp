@@ -42,8 +42,8 @@ struct KArgs {
 // Update strip width (columns of the logical C tile per work unit).
 inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
 
-// One V/T record: V and V^T (nb x nb each) and nb/16 blocks T_b^T (16 x 16).
-inline int64_t record_doubles(int nb) { return 2LL * nb * nb + 16LL * nb; }
+// One V/T record: V (nb x nb) and nb/16 blocks T_b^T (16 x 16).
+inline int64_t record_doubles(int nb) { return 1LL * nb * nb + 16LL * nb; }
 
 // Launchers (return hipSuccess or the launch error).
 // Resets the scheduler words and the dependency counters.

@@ -61,7 +61,7 @@ def test_workspace_sizes():
     p = bb.Plan(1000, 700, 128, "auto", "rbidiag")
     st = p.stats()
     vt, ws = p.workspace()
-    assert vt == st["nslots"] * (2 * 128 * 128 + 16 * 128) * 8
+    assert vt == st["nslots"] * (128 * 128 + 16 * 128) * 8
     assert ws >= 4 * st["ntasks"]
     assert st["p"] == 8 and st["q"] == 6
 
@@ -261,14 +261,14 @@ def test_batch_plan_layout_and_tuning_table():
         single = bb.Plan(m, n, nb, info["tree"], info["variant"])
         assert info["nrec"] == single.stats()["nslots"]
         total += single.workspace()[0]
-        rec = 8 * (2 * nb * nb + 16 * nb)
+        rec = 8 * (nb * nb + 16 * nb)
         assert info["rec_offset"] % rec == 0 or info["rec_offset"] % 256 == 0
         assert info["rec_offset"] + info["nrec"] * rec <= vt
     assert vt >= total
     # records of different matrices do not overlap
     spans = sorted((plan.info(i)["rec_offset"],
                     plan.info(i)["rec_offset"] + plan.info(i)["nrec"] * 8 *
-                    (2 * nbs[i] ** 2 + 16 * nbs[i])) for i in range(len(shapes)))
+                    (nbs[i] ** 2 + 16 * nbs[i])) for i in range(len(shapes)))
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
         assert a1 <= b0
     # tuned choices are valid and cover the whole range of sizes
