@@ -208,6 +208,38 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
+// sqrt(t) and 1/x for positive normal t and nonzero normal x: the hardware
+// approximations refined by Newton steps (within an ulp, without the special
+// value and scaling paths of the IEEE library forms, which the Householder
+// steps never need).
+__device__ __forceinline__ double refined_sqrt(double t) {
+    const double r = __builtin_amdgcn_rsq(t);
+    double s = t * r, h = 0.5 * r;
+    const double e = fma(-h, s, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    double d = fma(-s, s, t);
+    s = fma(d, h, s);
+    d = fma(-s, s, t);
+    return fma(d, h, s);
+}
+
+__device__ __forceinline__ double refined_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Value of lane `src` (wave-uniform) of a double.
+__device__ __forceinline__ double readlane64(double v, int src) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Panel kernels: GEQRT, TSQRT, TTQRT (Table 1), blocked by 16 columns.
 //
@@ -299,16 +331,18 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                     for (int s = 0; s + h < SR; s += 2 * h) sq[s] += sq[s + h];
                 if (PAIR && lq == c) al = r1;
                 const double ss = sum16(sq[0]);
-                al = sum16(al);
+                // alpha sits in the lane with row phase c of this column's
+                // 16 lanes (lane 16 (c % 4) + c of the wave): read it there.
+                al = readlane64(al, 16 * (c & 3) + c);
                 double tau = 0.0, beta = al, scale = 0.0;
                 if (ss != 0.0) {
                     // tau = (beta - al) / beta and scale = 1 / (al - beta)
-                    // from one division: with d = al - beta,
+                    // from one reciprocal: with d = al - beta,
                     // 1 / (beta d) gives tau = -d^2 / (beta d) and scale = beta / (beta d).
-                    const double nrm = sqrt(fma(al, al, ss));
+                    const double nrm = refined_sqrt(fma(al, al, ss));
                     beta = al >= 0.0 ? -nrm : nrm;
                     const double d = al - beta;
-                    const double inv = 1.0 / (beta * d);
+                    const double inv = refined_rcp(beta * d);
                     tau = -(d * d) * inv;
                     scale = beta * inv;
                 }
