@@ -191,8 +191,8 @@ struct Rec {
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
@@ -365,15 +365,16 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 if (lq == 0) taus[c] = tau;
             }
             lds_barrier();
+            // the reflector and tau_c are read together (one LDS latency)
             const double tc = taus[c];
+            double vv[SR];
+#pragma unroll
+            for (int s = 0; s < SR; ++s) vv[s] = vb[lq + 16 * s];
             if (lj != c) {
                 if (tc != 0.0) {
-                    double vv[SR], dp[2] = {0.0, 0.0};
+                    double dp[2] = {0.0, 0.0};
 #pragma unroll
-                    for (int s = 0; s < SR; ++s) {
-                        vv[s] = vb[lq + 16 * s];
-                        dp[s & 1] = fma(vv[s], x[s], dp[s & 1]);
-                    }
+                    for (int s = 0; s < SR; ++s) dp[s & 1] = fma(vv[s], x[s], dp[s & 1]);
                     double d = dp[0] + dp[1];
                     if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
                     d = sum16(d);
