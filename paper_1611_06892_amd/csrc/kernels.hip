@@ -21,6 +21,8 @@
 // updates apply the 16-column blocks of a panel's reflectors with FP64 MFMA
 // (v_mfma_f64_16x16x4) to register-resident 16-column slices of the trailing
 // tile(s).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace bbk {
@@ -259,7 +261,8 @@ __device__ __forceinline__ double readlane64(double v, int src) {
 //     T_b (16 x 16 upper, Q_b = I - U_b T_b U_b^T) follows by the forward
 //     recurrence T(c,c) = tau_c, T(0:c-1,c) = -tau_c T(0:c-1,0:c-1) G(0:c-1,c).
 //  2. trailing: Q_b^T is applied to the column tiles right of the block with
-//     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W).
+//     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W);
+//     T_b is formed on the vector units while the first product runs.
 //     Column tile J lives in registers of wave J % 4 for the whole kernel.
 // Record (FP64): V (nb x nb, column-major), then the nb/16 blocks T_b^T
 // (16 x 16 column-major) -- the same blocked compact-WY form the update
@@ -313,105 +316,119 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
         double r1 = 0.0;                    // PAIR: R1(16b + lq, 16b + lj)
         if (PAIR) r1 = T1.get(16 * b + lq, 16 * b + lj);
-        for (int c = 0; c < 16; ++c) {
-            const int cc = 16 * b + c;
-            double* vb = vbuf + (c & 1) * NB;
-            if (lj == c) {
-                double sq[SR], al = 0.0;
+        // The column loop is instantiated per block index B, which fixes at
+        // compile time where each register slot s (rows lq + 16 s) lies
+        // relative to the block's diagonal rows 16 B .. 16 B + 15: only slot B
+        // straddles the diagonal and needs per-lane masks.  Slots that can
+        // hold no reflector entry (above the diagonal block for GEQRT, below
+        // it for the triangle of TTQRT) are left out of every step.
+        auto leaf = [&](auto bconst) {
+            constexpr int B = decltype(bconst)::value;
+            if constexpr (B < MT) {
+                constexpr int S0 = PAIR ? 0 : B;        // live slots [S0, S1)
+                constexpr int S1 = TT ? B + 1 : SR;
+                constexpr int NL = S1 - S0;
+                for (int c = 0; c < 16; ++c) {
+                    double* vb = vbuf + (c & 1) * NB;
+                    if (lj == c) {
+                        // Reflector entry in slot s: rows below the diagonal
+                        // (GEQRT), the whole tile (TSQRT) or rows up to it (TTQRT).
+                        auto tail = [&](int s) {
+                            if (!PAIR) return s > B || lq > c;
+                            if (TT) return s < B || lq <= c;
+                            return true;
+                        };
+                        double q[NL], al = 0.0;
 #pragma unroll
-                for (int s = 0; s < SR; ++s) {
-                    const int row = lq + 16 * s;
-                    const bool tail = PAIR ? (!TT || row <= cc) : row > cc;
-                    sq[s] = tail ? x[s] * x[s] : 0.0;
-                    if (!PAIR && row == cc) al = x[s];
-                }
+                        for (int k = 0; k < NL; ++k) {
+                            const int s = S0 + k;
+                            q[k] = tail(s) ? x[s] * x[s] : 0.0;
+                        }
+                        if (!PAIR && lq == c) al = x[B];
 #pragma unroll
-                for (int h = 1; h < SR; h *= 2)
+                        for (int h = 1; h < NL; h *= 2)
 #pragma unroll
-                    for (int s = 0; s + h < SR; s += 2 * h) sq[s] += sq[s + h];
-                if (PAIR && lq == c) al = r1;
-                const double ss = sum16(sq[0]);
-                // alpha sits in the lane with row phase c of this column's
-                // 16 lanes (lane 16 (c % 4) + c of the wave): read it there.
-                al = readlane64(al, 16 * (c & 3) + c);
-                double tau = 0.0, beta = al, scale = 0.0;
-                if (ss != 0.0) {
-                    // tau = (beta - al) / beta and scale = 1 / (al - beta)
-                    // from one reciprocal: with d = al - beta,
-                    // 1 / (beta d) gives tau = -d^2 / (beta d) and scale = beta / (beta d).
-                    const double nrm = refined_sqrt(fma(al, al, ss));
-                    beta = al >= 0.0 ? -nrm : nrm;
-                    const double d = al - beta;
-                    const double inv = refined_rcp(beta * d);
-                    tau = -(d * d) * inv;
-                    scale = beta * inv;
-                }
+                            for (int k = 0; k + h < NL; k += 2 * h) q[k] += q[k + h];
+                        if (PAIR && lq == c) al = r1;
+                        const double ss = sum16(q[0]);
+                        // alpha sits in the lane with row phase c of this column's
+                        // 16 lanes (lane 16 (c % 4) + c of the wave): read it there.
+                        al = readlane64(al, 16 * (c & 3) + c);
+                        double tau = 0.0, beta = al, scale = 0.0;
+                        if (ss != 0.0) {
+                            // tau = (beta - al) / beta and scale = 1 / (al - beta)
+                            // from one reciprocal: with d = al - beta,
+                            // 1 / (beta d) gives tau = -d^2 / (beta d) and scale = beta / (beta d).
+                            const double nrm = refined_sqrt(fma(al, al, ss));
+                            beta = al >= 0.0 ? -nrm : nrm;
+                            const double d = al - beta;
+                            const double inv = refined_rcp(beta * d);
+                            tau = -(d * d) * inv;
+                            scale = beta * inv;
+                        }
 #pragma unroll
-                for (int s = 0; s < SR; ++s) {
-                    const int row = lq + 16 * s;
-                    double vv;
-                    if (PAIR) {
-                        const bool tail = !TT || row <= cc;
-                        if (tail) x[s] *= scale;
-                        vv = tail ? x[s] : 0.0;
-                    } else {
-                        if (row > cc) x[s] *= scale;
-                        if (row == cc) x[s] = beta;
-                        vv = row > cc ? x[s] : (row == cc ? 1.0 : 0.0);
+                        for (int k = 0; k < NL; ++k) {
+                            const int s = S0 + k;
+                            double vv;
+                            if (!PAIR && s == B) {
+                                const bool t = lq > c, dg = lq == c;
+                                if (t) x[s] *= scale;
+                                if (dg) x[s] = beta;
+                                vv = t ? x[s] : (dg ? 1.0 : 0.0);
+                            } else if (TT && s == B) {
+                                const bool t = lq <= c;
+                                if (t) x[s] *= scale;
+                                vv = t ? x[s] : 0.0;
+                            } else {
+                                x[s] *= scale;
+                                vv = x[s];
+                            }
+                            vb[lq + 16 * s] = vv;
+                        }
+                        if (PAIR && lq == c) r1 = beta;
+                        if (lq == 0) taus[c] = tau;
                     }
-                    vb[row] = vv;
-                }
-                if (PAIR && lq == c) r1 = beta;
-                if (lq == 0) taus[c] = tau;
-            }
-            lds_barrier();
-            // the reflector and tau_c are read together (one LDS latency)
-            const double tc = taus[c];
-            double vv[SR];
+                    lds_barrier();
+                    // the reflector and tau_c are read together (one LDS latency)
+                    const double tc = taus[c];
+                    double vv[SR];
 #pragma unroll
-            for (int s = 0; s < SR; ++s) vv[s] = vb[lq + 16 * s];
-            if (lj != c) {
-                if (tc != 0.0) {
-                    double dp[2] = {0.0, 0.0};
+                    for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
+                    // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
+                    // every T entry that G(:, c) feeds.
+                    if (lj != c) {
+                        double dp[2] = {0.0, 0.0};
 #pragma unroll
-                    for (int s = 0; s < SR; ++s) dp[s & 1] = fma(vv[s], x[s], dp[s & 1]);
-                    double d = dp[0] + dp[1];
-                    if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
-                    d = sum16(d);
-                    if (lj > c) {
-                        const double wv = tc * d;
+                        for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
+                        double d = dp[0] + dp[1];
+                        if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                        d = sum16(d);
+                        if (lj > c) {
+                            const double wv = tc * d;
 #pragma unroll
-                        for (int s = 0; s < SR; ++s) x[s] -= wv * vv[s];
-                        if (PAIR && lq == c) r1 -= wv;
-                    } else if (lq == 0) {
-                        Gs[lj + 16 * c] = d;            // u_lj . u_c
+                            for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
+                            if (PAIR && lq == c) r1 -= wv;
+                        } else if (lq == 0) {
+                            Gs[lj + 16 * c] = d;            // u_lj . u_c
+                        }
                     }
                 }
             }
+        };
+        static_assert(MT <= 8, "block index dispatch covers nb <= 128");
+        switch (b) {
+            case 0: leaf(std::integral_constant<int, 0>{}); break;
+            case 1: leaf(std::integral_constant<int, 1>{}); break;
+            case 2: leaf(std::integral_constant<int, 2>{}); break;
+            case 3: leaf(std::integral_constant<int, 3>{}); break;
+            case 4: leaf(std::integral_constant<int, 4>{}); break;
+            case 5: leaf(std::integral_constant<int, 5>{}); break;
+            case 6: leaf(std::integral_constant<int, 6>{}); break;
+            default: leaf(std::integral_constant<int, 7>{}); break;
         }
-        lds_barrier();
-        // T_b by the forward recurrence T(c,c) = tau_c,
-        // T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c), with thread (i, l) =
-        // (tid/16, tid%16) holding T(i,l): one product and a row sum per column.
-        {
-            const int i = lj, l = lq;
-            double gl[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) gl[c] = Gs[l + 16 * c];
-            double til = 0.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const double tcv = taus[c];
-                const double sm = sum16((l >= i && l < c) ? til * gl[c] : 0.0);
-                const double tic = c < i ? 0.0 : (c == i ? tcv : -tcv * sm);
-                if (l == c) til = tic;
-            }
-            TbT[l + 16 * i] = til;       // T(i, l)
-        }
-        lds_barrier();
-        gstore<CO>(gTt + 256 * b + tid, ((tid & 15) < (tid >> 4)) ? 0.0 : TbT[tid]);
-        // Leaf outputs: explicit U_b tails into the leaf buffer and the record,
-        // R (GEQRT) or zeros (TS/TT) into the matrix.
+        // Leaf outputs, each thread on the leaf slots it read: explicit U_b
+        // into the leaf buffer and the record, R (GEQRT) or zeros (TS/TT)
+        // into the matrix.
         {
             const int col = 16 * b + lj;
 #pragma unroll
@@ -428,36 +445,83 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         }
         lds_barrier();
 
-        // 2. Trailing update of the column tiles right of block b.
+        // 2. Trailing update of the column tiles right of block b.  The
+        // products W = R1 + U_b^T X run on the matrix cores while the vector
+        // units form T_b by the forward recurrence T(c,c) = tau_c,
+        // T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c), thread (i, l) =
+        // (tid/16, tid%16) holding T(i,l): one product and a row sum per column.
+        bool act[OWN];
+        d4 R1b[OWN], W[OWN];
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
             const int J = w + 4 * o;
-            if (J < MT && J > b) {
-                d4 R1b = {0.0, 0.0, 0.0, 0.0};
-                if (PAIR) R1b = load16(T1, 16 * b, 16 * J);
-                d4 W = R1b;
+            act[o] = J < MT && J > b;
+            R1b[o] = d4{0.0, 0.0, 0.0, 0.0};
+            if (PAIR && act[o]) R1b[o] = load16(T1, 16 * b, 16 * J);
+            W[o] = R1b[o];
+        }
+        double gl[16];
 #pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    if (!PAIR && i < b) continue;
-                    if (TT && i > b) continue;
+        for (int c = 0; c < 16; ++c) gl[c] = Gs[lq + 16 * c];
+        double til = 0.0;
+        constexpr int TSTEP = 16 / MT;      // recurrence columns per 16-row step
+        double la[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) W = mfma(Lf[(16 * i + 4 * r + g) + j * LDL], xt[o][i][r], W);
-                    SCHED_FENCE();
+        for (int r = 0; r < 4; ++r) la[r] = Lf[(4 * r + g) + j * LDL];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            double ln[4];
+            if (i + 1 < MT) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ln[r] = Lf[(16 * (i + 1) + 4 * r + g) + j * LDL];
+            }
+            const bool rows = (PAIR || i >= b) && (!TT || i <= b);
+#pragma unroll
+            for (int o = 0; o < OWN; ++o)
+                if (act[o] && rows) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) W[o] = mfma(la[r], xt[o][i][r], W[o]);
                 }
+#pragma unroll
+            for (int u = 0; u < TSTEP; ++u) {
+                const int c = TSTEP * i + u;
+                const double tcv = taus[c];
+                const double sm = sum16((lq >= lj && lq < c) ? til * gl[c] : 0.0);
+                const double tic = c < lj ? 0.0 : (c == lj ? tcv : -tcv * sm);
+                if (lq == c) til = tic;
+            }
+            SCHED_FENCE();
+            if (i + 1 < MT) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) la[r] = ln[r];
+            }
+        }
+        TbT[lq + 16 * lj] = til;            // T(i, l)
+        gstore<CO>(gTt + 256 * b + tid, til);
+        lds_barrier();
+#pragma unroll
+        for (int o = 0; o < OWN; ++o)
+            if (act[o]) {
                 d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
-                if (PAIR) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
-#pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    if (!PAIR && i < b) continue;
-                    if (TT && i > b) continue;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        xt[o][i] = mfma(-Lf[(16 * i + j) + (4 * r + g) * LDL], W2[r], xt[o][i]);
-                    SCHED_FENCE();
-                }
+                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[o][r], W2);
+                if (PAIR) store16<CO>(T1, 16 * b, 16 * (w + 4 * o), R1b[o] - W2);
+                W[o] = W2;
             }
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            if (!PAIR && i < b) continue;
+            if (TT && i > b) continue;
+            double lu[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lu[r] = -Lf[(16 * i + j) + (4 * r + g) * LDL];
+#pragma unroll
+            for (int o = 0; o < OWN; ++o)
+                if (act[o]) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xt[o][i] = mfma(lu[r], W[o][r], xt[o][i]);
+                }
+            SCHED_FENCE();
         }
         lds_barrier();
     }
