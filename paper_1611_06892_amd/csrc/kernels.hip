@@ -394,6 +394,10 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                     double vv[SR];
 #pragma unroll
                     for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
+                    // tau_c is needed only after the dot product's reduction;
+                    // holding it here keeps its read in the same batch as the
+                    // reflector's instead of after the reduction.
+                    asm volatile("" ::"v"(tc));
                     // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
                     // every T entry that G(:, c) feeds.
                     if (lj != c) {
