@@ -242,6 +242,108 @@ __device__ __forceinline__ double readlane64(double v, int src) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+// The unit a workgroup of the persistent scheduler finished last, whose
+// output stores may still be in flight.  The next unit retires it once its own
+// first loads are issued, so that the store drain and the load latency
+// overlap: every wave waits for all of its memory operations, then thread 0
+// counts the unit as done.
+struct Prev {
+    int task;                      // -1: nothing to retire
+    int ticket;
+    uint64_t wait, run, end;       // trace times of the finished unit
+};
+
+__device__ __forceinline__ int aload(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0, after the unit's outputs are complete: count down the
+// successors' dependency counters, then count the unit as done.
+__device__ __forceinline__ void complete_unit(const KArgs& a, int task) {
+    const int s0 = a.succ_off[task], s1 = a.succ_off[task + 1];
+    for (int e = s0; e < s1; ++e)
+        __hip_atomic_fetch_add(&a.deps[a.succ_idx[e]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&a.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of wave 0 (the results are the same in every lane).
+// take_ticket: the next priority position, or -1 when all are taken.
+// unit_ready: whether that unit's task has no unfinished predecessor now.
+// wait_unit: wait until it has none; returns the ticket, or -1 to stop.
+__device__ __forceinline__ int take_ticket(const KArgs& a, int lane) {
+    int u = 0;
+    if (lane == 0)
+        u = __hip_atomic_fetch_add(&a.ctrl[CTRL_HEAD], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    u = __builtin_amdgcn_readfirstlane(u);
+    return u >= a.nunits ? -1 : u;
+}
+
+__device__ __forceinline__ bool unit_ready(const KArgs& a, int u, int lane) {
+    const int task = __builtin_amdgcn_readfirstlane(a.units[u].x);
+    int d = 0;
+    if (lane == 0) d = aload(&a.deps[task]);
+    return __builtin_amdgcn_readfirstlane(d) <= 0;
+}
+
+__device__ __forceinline__ int wait_unit(const KArgs& a, int u, int lane) {
+    const int task = __builtin_amdgcn_readfirstlane(a.units[u].x);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        int d = 0, err = 0;
+        if (lane == 0) {
+            d = aload(&a.deps[task]);
+            if (d > 0) err = aload(&a.ctrl[CTRL_ERROR]);
+        }
+        d = __builtin_amdgcn_readfirstlane(d);
+        if (d <= 0) return u;
+        if (__builtin_amdgcn_readfirstlane(err) != 0) return -1;
+        if ((int64_t)(wall_clock64() - t0) > a.watchdog_ticks) {
+            if (lane == 0) __hip_atomic_store(&a.ctrl[CTRL_ERROR], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Scheduler words in LDS (persistent kernel): the next ticket, whether its
+// unit was ready when taken, and the wall-clock time it was taken at.
+enum : int { SCH_TICKET = 0, SCH_READY = 1, SCH_TIME = 2, SCH_WORDS = 4 };
+
+// Wave 0 takes the next ticket and checks its unit once.  An update kernel
+// does this before its final stores: a wait for the returned values then
+// does not also wait for those stores (one in-order counter covers loads and
+// stores), and the next unit's loads can be issued while they drain.
+__device__ __forceinline__ void take_next(const KArgs& a, int* sch) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const uint64_t tw = wall_clock64();
+        const int u = take_ticket(a, lane);
+        const bool ready = u >= 0 && unit_ready(a, u, lane);
+        if (lane == 0) {
+            sch[SCH_TICKET] = u;
+            sch[SCH_READY] = ready;
+            *(uint64_t*)(sch + SCH_TIME) = tw;
+        }
+    }
+}
+
+__device__ __forceinline__ void retire(const KArgs& a, Prev& p) {
+    if (p.task < 0) return;        // uniform
+    __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier();
+    if (threadIdx.x == 0) {
+        if (a.trace != nullptr) {
+            int64_t* tr = a.trace + 4 * (int64_t)p.ticket;
+            tr[0] = (int64_t)p.wait;
+            tr[1] = (int64_t)p.run;
+            tr[2] = (int64_t)p.end;
+            tr[3] = blockIdx.x;
+        }
+        complete_unit(a, p.task);
+    }
+    p.task = -1;
+}
+
 // ---------------------------------------------------------------------------
 // Panel kernels: GEQRT, TSQRT, TTQRT (Table 1), blocked by 16 columns.
 //
@@ -269,7 +371,7 @@ __device__ __forceinline__ double readlane64(double v, int src) {
 // kernels apply.
 // ---------------------------------------------------------------------------
 template <int NB, int KIND, bool CO>
-__device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds) {
+__device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
     using S = Shape<NB>;
     constexpr int MT = S::MT, LDL = S::LDL;
     constexpr int OWN = (MT + 3) / 4;       // column tiles per wave
@@ -294,6 +396,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 #pragma unroll
     for (int o = 0; o < OWN; ++o)
         if (w + 4 * o < MT) load_slice<MT>(TX, 16 * (w + 4 * o), xt[o]);
+    retire(a, prev);
 
     for (int b = 0; b < MT; ++b) {
         // Column tile b goes to the leaf buffer.
@@ -547,7 +650,8 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 // T_b^T.
 // ---------------------------------------------------------------------------
 template <int NB, int KIND, bool CO, bool HQ>
-__device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds) {
+__device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
+                                       int* sch) {
     constexpr int MT = NB / 16;
     constexpr int NS = NB >= 64 ? 64 : NB;
     constexpr int LDV = NB + 1;
@@ -584,6 +688,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     if (active) load_slice<MT>(T2, c0, c2);
     double pre[PRE];
     fetch(blk(0), pre);
+    retire(a, prev);
     stage(0, pre);
     d4 C1n = {0.0, 0.0, 0.0, 0.0};
     if (HASC1 && active) C1n = load16(T1, 16 * blk(0), c0);
@@ -625,6 +730,7 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
         if (st + 1 < MT) stage((st + 1) & 1, pre);
         lds_barrier();
     }
+    if (sch != nullptr) take_next(a, sch);
     if (active) store_slice<CO, MT>(T2, c0, c2);
 }
 
@@ -684,7 +790,8 @@ __device__ __forceinline__ void store16_r4(const TileView& t, int r0, int c0, d4
 __device__ __forceinline__ float lo32(double x, float hi) { return (float)(x - (double)hi); }
 
 template <int NB, int KIND, bool CO, bool SPLIT>
-__device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int part, double* lds) {
+__device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
+                                         int* sch) {
     constexpr int MT = NB / 16;
     constexpr int NS = NB >= 64 ? 64 : NB;
     constexpr int LDV = NB + 1;
@@ -735,6 +842,7 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
     if (active) load_slice_r4<MT>(T2, c0, c2);
     double pre[PRE];
     fetch(0, pre);
+    retire(a, prev);
     stage(0, pre);
     d4 C1n = {0.0, 0.0, 0.0, 0.0};
     if (HASC1 && active) C1n = load16_r4(T1, 0, c0);
@@ -793,41 +901,43 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
         if (b + 1 < MT) stage(b + 1, pre);
         lds_barrier();
     }
+    if (sch != nullptr) take_next(a, sch);
     if (active) store_slice_r4<CO, MT>(T2, c0, c2);
 }
 
 // PREC: 0 = FP64 updates, 2 = FP32-MFMA updates, 3 = split-FP32 updates.
 template <int NB, bool CO, int PREC>
-__device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds) {
+__device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds, Prev& prev, int* sch) {
     const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
     switch (tk.kind) {
-    case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds); break;
-    case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds); break;
-    case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds); break;
+    case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds, prev); break;
+    case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds, prev); break;
+    case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds, prev); break;
     case K_UNMQR:
-        if (PREC == 0) update<NB, K_UNMQR, CO, false>(a, tk, part, lds);
-        else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_UNMQR, CO, false>(a, tk, part, lds, prev, sch);
+        else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
         break;
     case K_TSMQR:
-        if (PREC == 0) update<NB, K_TSMQR, CO, false>(a, tk, part, lds);
-        else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_TSMQR, CO, false>(a, tk, part, lds, prev, sch);
+        else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
         break;
     case K_TTMQR:
-        if (PREC == 0) update<NB, K_TTMQR, CO, false>(a, tk, part, lds);
-        else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_TTMQR, CO, false>(a, tk, part, lds, prev, sch);
+        else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
         break;
     // Applications of Q itself (records of a finished reduction, FP64 only;
     // the host builds them for PREC 0 alone).
     case K_UNMQR + K_HQ:
-        if (PREC == 0) update<NB, K_UNMQR, CO, true>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_UNMQR, CO, true>(a, tk, part, lds, prev, sch);
         break;
     case K_TSMQR + K_HQ:
-        if (PREC == 0) update<NB, K_TSMQR, CO, true>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_TSMQR, CO, true>(a, tk, part, lds, prev, sch);
         break;
     default:
-        if (PREC == 0) update<NB, K_TTMQR, CO, true>(a, tk, part, lds);
+        if (PREC == 0) update<NB, K_TTMQR, CO, true>(a, tk, part, lds, prev, sch);
         break;
     }
+    retire(a, prev);               // a kind that ran nothing
 }
 
 }  // namespace
@@ -837,7 +947,8 @@ template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
     __shared__ double lds[Shape<NB>::LDS];
     const int2 u = a.units[unit_base + blockIdx.x];
-    run_unit<NB, false, PREC>(a, u.x, u.y, lds);
+    Prev none{-1, 0, 0, 0, 0};
+    run_unit<NB, false, PREC>(a, u.x, u.y, lds, none, nullptr);
 }
 
 // Persistent scheduler.  The work units are listed in one priority order:
@@ -850,88 +961,55 @@ __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
 // earliest unfinished ticket can always proceed: no deadlock for any grid
 // size.  A wall-clock watchdog bounds every wait (error 3 after watchdog_ticks),
 // and an error reported by any workgroup stops all of them.
-__device__ __forceinline__ int aload(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by all 64 lanes of wave 0; returns the same value in every lane:
-// a ticket (priority position) whose unit is ready, or -1 to stop.
-__device__ __forceinline__ int next_unit(const KArgs& a, int lane) {
-    int u = 0;
-    if (lane == 0)
-        u = __hip_atomic_fetch_add(&a.ctrl[CTRL_HEAD], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    u = __builtin_amdgcn_readfirstlane(u);
-    if (u >= a.nunits) return -1;
-    const int task = __builtin_amdgcn_readfirstlane(a.units[u].x);
-    const uint64_t t0 = wall_clock64();
-    for (;;) {
-        int d = 0, err = 0;
-        if (lane == 0) {
-            d = aload(&a.deps[task]);
-            if (d > 0) err = aload(&a.ctrl[CTRL_ERROR]);
-        }
-        d = __builtin_amdgcn_readfirstlane(d);
-        if (d <= 0) return u;
-        if (__builtin_amdgcn_readfirstlane(err) != 0) return -1;
-        if ((int64_t)(wall_clock64() - t0) > a.watchdog_ticks) {
-            if (lane == 0) __hip_atomic_store(&a.ctrl[CTRL_ERROR], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return -1;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
-
-// Thread 0, after the unit's outputs are complete: count down the
-// successors' dependency counters, then count the unit as done.
-__device__ __forceinline__ void complete_unit(const KArgs& a, int task) {
-    const int s0 = a.succ_off[task], s1 = a.succ_off[task + 1];
-    for (int e = s0; e < s1; ++e)
-        __hip_atomic_fetch_add(&a.deps[a.succ_idx[e]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&a.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
-    __shared__ double lds[Shape<NB>::LDS];
-    __shared__ int s_unit;
-    __shared__ uint64_t s_wait;
+    __shared__ double lds[Shape<NB>::LDS + SCH_WORDS / 2];
+    int* sch = (int*)(lds + Shape<NB>::LDS);
     const int tid = threadIdx.x;
+    Prev prev{-1, 0, 0, 0, 0};
+    if (tid == 0) sch[SCH_TICKET] = -2;     // -2: no ticket taken yet
     for (;;) {
-        if (tid < 64) {
-            const uint64_t tw = wall_clock64();
-            const int unit = next_unit(a, tid);
-            if (tid == 0) {
-                s_unit = unit;
-                s_wait = tw;
-            }
-        }
-        __syncthreads();
+        lds_barrier();
+        if (__builtin_amdgcn_readfirstlane(sch[SCH_TICKET]) == -2) take_next(a, sch);
+        lds_barrier();
         // Uniform in the workgroup; readfirstlane lets the compiler see that,
         // which keeps the loop's exits uniform.
-        const int u = __builtin_amdgcn_readfirstlane(s_unit);
+        int u = __builtin_amdgcn_readfirstlane(sch[SCH_TICKET]);
+        const bool ready = __builtin_amdgcn_readfirstlane(sch[SCH_READY]) != 0;
+        const uint64_t t_wait = *(const uint64_t*)(sch + SCH_TIME);
+        lds_barrier();
+        if (tid == 0) sch[SCH_TICKET] = -2;
+        // Never wait while holding an unfinished unit: its successors may be
+        // the units waited for.
+        if (!ready) retire(a, prev);
         if (u < 0) break;
+        if (!ready) {
+            if (tid < 64) {
+                const int r = wait_unit(a, u, tid);
+                if (tid == 0) sch[SCH_READY] = r;
+            }
+            lds_barrier();
+            u = __builtin_amdgcn_readfirstlane(sch[SCH_READY]);
+            if (u < 0) break;
+        }
         const int2 un0 = a.units[u];
         const int2 un = make_int2(__builtin_amdgcn_readfirstlane(un0.x),
                                   __builtin_amdgcn_readfirstlane(un0.y));
         // Acquire: drop stale lines of the inputs from this CU's caches and
-        // this XCD's L2.  Release: the unit wrote its outputs with agent-scope
-        // stores, so waiting for them to complete publishes them to every XCD.
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // this XCD's L2 (the predecessors' completion was observed above).
+        // Release: a unit writes its outputs with agent-scope stores, and
+        // waiting for them to complete publishes them to every XCD.  The
+        // invalidation is issued without the full memory wait a fence would
+        // add, which would also wait for the previous unit's stores.
+        asm volatile("buffer_inv sc1" ::: "memory");
         const uint64_t t_run = a.trace != nullptr && tid == 0 ? wall_clock64() : 0;
-        run_unit<NB, true, PREC>(a, un.x, un.y, lds);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid == 0) {
-            if (a.trace != nullptr) {
-                int64_t* tr = a.trace + 4 * (int64_t)u;
-                tr[0] = (int64_t)s_wait;
-                tr[1] = (int64_t)t_run;
-                tr[2] = (int64_t)wall_clock64();
-                tr[3] = blockIdx.x;
-            }
-            complete_unit(a, un.x);
-        }
-        __syncthreads();
+        run_unit<NB, true, PREC>(a, un.x, un.y, lds, prev, sch);
+        prev.task = un.x;
+        prev.ticket = u;
+        prev.wait = t_wait;
+        prev.run = t_run;
+        prev.end = a.trace != nullptr && tid == 0 ? wall_clock64() : 0;
     }
 }
 
