@@ -717,14 +717,16 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
             // Ts holds T_b^T column-major: T_b(k, i) at i + 16 k.
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                W2 = mfma(HQ ? Ts[(4 * r + g) + 16 * j] : Ts[j + 16 * (4 * r + g)], W[r], W2);
-            if (HASC1) store16<CO>(T1, 16 * b, c0, C1b - W2);
+                W2 = mfma(-(HQ ? Ts[(4 * r + g) + 16 * j] : Ts[j + 16 * (4 * r + g)]), W[r], W2);
+            // W2 holds -T_b^T W: negating the 4 T operands spares negating
+            // the 32 V operands of the update below.
+            if (HASC1) store16<CO>(T1, 16 * b, c0, C1b + W2);
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
                 if (KIND == K_UNMQR && i < b) continue;
                 if (KIND == K_TTMQR && i > b) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) c2[i] = mfma(-Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
+                for (int r = 0; r < 4; ++r) c2[i] = mfma(Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
             }
         }
         if (st + 1 < MT) stage((st + 1) & 1, pre);
