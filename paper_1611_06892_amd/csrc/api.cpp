@@ -89,9 +89,9 @@ const double kUnit[bb::NKINDS] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0, 6.0, 12.0, 6.0}
 // task with its column strips run side by side).  Unlike Table 1, whose unit
 // is flops, it reflects that a panel is a chain of nb dependent Householder
 // steps while an update is throughput-bound MFMA work (measured on MI355X for
-// nb = 128 in a loaded run: panels ~160-175 us, UNMQR / TSMQR / TTMQR strips
-// ~25 / 37 / 36 us).
-const double kGpuCost[bb::NKINDS] = {16.0, 17.0, 17.0, 2.5, 3.7, 3.6, 2.5, 3.7, 3.6};
+// nb = 128 in a loaded run: GEQRT / TSQRT / TTQRT panels ~100 / 135 / 120 us,
+// UNMQR / TSMQR / TTMQR strips ~25 / 37 / 32 us).
+const double kGpuCost[bb::NKINDS] = {10.0, 13.5, 12.0, 2.5, 3.7, 3.2, 2.5, 3.7, 3.2};
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -961,8 +961,11 @@ __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
 // until the unit's task has no unfinished predecessor unit.  Tickets go only
 // to running workgroups and every predecessor holds an earlier ticket, so the
 // earliest unfinished ticket can always proceed: no deadlock for any grid
-// size.  A wall-clock watchdog bounds every wait (error 3 after watchdog_ticks),
-// and an error reported by any workgroup stops all of them.
+// size.  A finished unit is counted done only after the workgroup's next unit
+// has issued its first loads (its output stores drain meanwhile), and never
+// later than the workgroup's next wait on a dependency, so that argument still
+// holds.  A wall-clock watchdog bounds every wait (error 3 after
+// watchdog_ticks), and an error reported by any workgroup stops all of them.
 
 template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
