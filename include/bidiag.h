@@ -71,8 +71,8 @@ enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2 };
 enum { BB_F64 = 0, BB_F64_UPD_F32 = 2, BB_F64_UPD_SPLIT32 = 3 };
 /* Execution of the task graph: one persistent launch whose workgroups take
  * work units in a precomputed priority order (a list-scheduling simulation
- * on the GPU's workgroups, by bottom level in the task graph, R-BiDiag's
- * second phase first) and wait on dependency counters (default), or one
+ * on the GPU's workgroups, by bottom level in the task graph) and wait on
+ * dependency counters (default), or one
  * launch per topological level of the graph. */
 enum { BB_SCHED_PERSISTENT = 0, BB_SCHED_LEVELS = 1 };
 

@@ -150,15 +150,9 @@ int build_schedule(bb_plan& P) {
         for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) b = std::max(b, blevel[P.succ_idx[s]]);
         blevel[t] = b + kGpuCost[g.tasks[t].kind];
     }
-    // R-BiDiag: the band reduction of R (second phase) is a chain of panels
-    // that occupies few CUs while the QR(p,q) phase is throughput-bound, so
-    // its tasks go first whenever they are ready.
-    std::vector<double> prio(blevel);
-    if (g.phase2_start >= 0) {
-        double bmax = 0.0;
-        for (int t = 0; t < nt; ++t) bmax = std::max(bmax, blevel[t]);
-        for (int t = g.phase2_start; t < nt; ++t) prio[t] += bmax;
-    }
+    // Plain bottom levels for both variants: ranking R-BiDiag's second phase
+    // above QR(p,q) measured slightly slower for tall and square inputs.
+    const std::vector<double>& prio = blevel;
     P.cp = bb::critical_path(g, kUnit);
     P.total = 0.0;
     for (int t = 0; t < nt; ++t) P.total += kUnit[g.tasks[t].kind];
