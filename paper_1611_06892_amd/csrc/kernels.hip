@@ -16,11 +16,13 @@
 // of a panel are kept in compact WY form Q = H_1 ... H_k = I - V T V^T with T
 // upper triangular, and an update applies Q^T: C <- C - V T^T V^T C.
 //
-// One workgroup of 256 threads (4 wave64) executes one work unit.  Panels are
-// blocked by 16 columns (a register-resident leaf plus MFMA trailing updates);
-// updates apply the 16-column blocks of a panel's reflectors with FP64 MFMA
-// (v_mfma_f64_16x16x4) to register-resident 16-column slices of the trailing
-// tile(s).
+// One workgroup of 512 threads (8 wave64, two per SIMD) executes one work
+// unit.  Panels are blocked by 16 columns (a register-resident leaf on four
+// waves plus MFMA trailing updates on all eight); updates apply the 16-column
+// blocks of a panel's reflectors with FP64 MFMA (v_mfma_f64_16x16x4) to
+// register-resident 16-column slices of the trailing tile(s), one slice per
+// wave.  Two waves per SIMD let one wave's MFMA chain run while the other
+// waits on a dependency.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -29,7 +31,7 @@ namespace bbk {
 
 namespace {
 
-constexpr int NT = 256;          // threads per workgroup
+constexpr int NT = 512;          // threads per workgroup
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 enum : int { K_GEQRT = 0, K_TSQRT = 1, K_TTQRT = 2, K_UNMQR = 3, K_TSMQR = 4, K_TTMQR = 5, K_HQ = 3 };
@@ -374,7 +376,7 @@ template <int NB, int KIND, bool CO>
 __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
     using S = Shape<NB>;
     constexpr int MT = S::MT, LDL = S::LDL;
-    constexpr int OWN = (MT + 3) / 4;       // column tiles per wave
+    constexpr int OWN = (MT + 7) / 8;       // column tiles per wave
     constexpr int SR = NB / 16;             // leaf rows per thread
     constexpr bool PAIR = KIND != K_GEQRT;
     constexpr bool TT = KIND == K_TTQRT;
@@ -385,6 +387,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     double* TbT = Gs + 256;                 // T(k, i) at i + 16 k
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int lj = tid >> 4, lq = tid & 15; // leaf column, row phase
+    const bool lw = tid < 256;              // waves 0-3 run the leaf and form T_b
 
     const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
     const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
@@ -395,30 +398,32 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     d4 xt[OWN][MT];
 #pragma unroll
     for (int o = 0; o < OWN; ++o)
-        if (w + 4 * o < MT) load_slice<MT>(TX, 16 * (w + 4 * o), xt[o]);
+        if (w + 8 * o < MT) load_slice<MT>(TX, 16 * (w + 8 * o), xt[o]);
     retire(a, prev);
 
     for (int b = 0; b < MT; ++b) {
         // Column tile b goes to the leaf buffer.
-        if (w == (b & 3)) {
+        if (w == (b & 7)) {
 #pragma unroll
             for (int o = 0; o < OWN; ++o)
-                if (o == (b >> 2)) {
+                if (o == (b >> 3)) {
 #pragma unroll
                     for (int i = 0; i < MT; ++i)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) Lf[(16 * i + 4 * r + g) + j * LDL] = xt[o][i][r];
                 }
         }
-        Gs[tid] = 0.0;
+        if (lw) Gs[tid] = 0.0;
         lds_barrier();
 
         // 1. Leaf.
         double x[SR];
-#pragma unroll
-        for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
         double r1 = 0.0;                    // PAIR: R1(16b + lq, 16b + lj)
-        if (PAIR) r1 = T1.get(16 * b + lq, 16 * b + lj);
+        if (lw) {
+#pragma unroll
+            for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
+            if (PAIR) r1 = T1.get(16 * b + lq, 16 * b + lj);
+        }
         // The column loop is instantiated per block index B, which fixes at
         // compile time where each register slot s (rows lq + 16 s) lies
         // relative to the block's diagonal rows 16 B .. 16 B + 15: only slot B
@@ -433,7 +438,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 constexpr int NL = S1 - S0;
                 for (int c = 0; c < 16; ++c) {
                     double* vb = vbuf + (c & 1) * NB;
-                    if (lj == c) {
+                    if (lw && lj == c) {
                         // Reflector entry in slot s: rows below the diagonal
                         // (GEQRT), the whole tile (TSQRT) or rows up to it (TTQRT).
                         auto tail = [&](int s) {
@@ -492,31 +497,33 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                         if (lq == 0) taus[c] = tau;
                     }
                     lds_barrier();
-                    // the reflector and tau_c are read together (one LDS latency)
-                    const double tc = taus[c];
-                    double vv[SR];
+                    if (lw) {
+                        // the reflector and tau_c are read together (one LDS latency)
+                        const double tc = taus[c];
+                        double vv[SR];
 #pragma unroll
-                    for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
-                    // tau_c is needed only after the dot product's reduction;
-                    // holding it here keeps its read in the same batch as the
-                    // reflector's instead of after the reduction.
-                    asm volatile("" ::"v"(tc));
-                    // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
-                    // every T entry that G(:, c) feeds.
-                    if (lj != c) {
-                        double dp[2] = {0.0, 0.0};
+                        for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
+                        // tau_c is needed only after the dot product's reduction;
+                        // holding it here keeps its read in the same batch as the
+                        // reflector's instead of after the reduction.
+                        asm volatile("" ::"v"(tc));
+                        // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
+                        // every T entry that G(:, c) feeds.
+                        if (lj != c) {
+                            double dp[2] = {0.0, 0.0};
 #pragma unroll
-                        for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
-                        double d = dp[0] + dp[1];
-                        if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
-                        d = sum16(d);
-                        if (lj > c) {
-                            const double wv = tc * d;
+                            for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
+                            double d = dp[0] + dp[1];
+                            if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                            d = sum16(d);
+                            if (lj > c) {
+                                const double wv = tc * d;
 #pragma unroll
-                            for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
-                            if (PAIR && lq == c) r1 -= wv;
-                        } else if (lq == 0) {
-                            Gs[lj + 16 * c] = d;            // u_lj . u_c
+                                for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
+                                if (PAIR && lq == c) r1 -= wv;
+                            } else if (lq == 0) {
+                                Gs[lj + 16 * c] = d;            // u_lj . u_c
+                            }
                         }
                     }
                 }
@@ -536,7 +543,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         // Leaf outputs, each thread on the leaf slots it read: explicit U_b
         // into the leaf buffer and the record, R (GEQRT) or zeros (TS/TT)
         // into the matrix.
-        {
+        if (lw) {
             const int col = 16 * b + lj;
 #pragma unroll
             for (int s = 0; s < SR; ++s) {
@@ -561,15 +568,17 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         d4 R1b[OWN], W[OWN];
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
-            const int J = w + 4 * o;
+            const int J = w + 8 * o;
             act[o] = J < MT && J > b;
             R1b[o] = d4{0.0, 0.0, 0.0, 0.0};
             if (PAIR && act[o]) R1b[o] = load16(T1, 16 * b, 16 * J);
             W[o] = R1b[o];
         }
         double gl[16];
+        if (lw) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) gl[c] = Gs[lq + 16 * c];
+            for (int c = 0; c < 16; ++c) gl[c] = Gs[lq + 16 * c];
+        }
         double til = 0.0;
         constexpr int TSTEP = 16 / MT;      // recurrence columns per 16-row step
         double la[4];
@@ -589,13 +598,15 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 #pragma unroll
                     for (int r = 0; r < 4; ++r) W[o] = mfma(la[r], xt[o][i][r], W[o]);
                 }
+            if (lw) {
 #pragma unroll
-            for (int u = 0; u < TSTEP; ++u) {
-                const int c = TSTEP * i + u;
-                const double tcv = taus[c];
-                const double sm = sum16((lq >= lj && lq < c) ? til * gl[c] : 0.0);
-                const double tic = c < lj ? 0.0 : (c == lj ? tcv : -tcv * sm);
-                if (lq == c) til = tic;
+                for (int u = 0; u < TSTEP; ++u) {
+                    const int c = TSTEP * i + u;
+                    const double tcv = taus[c];
+                    const double sm = sum16((lq >= lj && lq < c) ? til * gl[c] : 0.0);
+                    const double tic = c < lj ? 0.0 : (c == lj ? tcv : -tcv * sm);
+                    if (lq == c) til = tic;
+                }
             }
             SCHED_FENCE();
             if (i + 1 < MT) {
@@ -603,8 +614,10 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 for (int r = 0; r < 4; ++r) la[r] = ln[r];
             }
         }
-        TbT[lq + 16 * lj] = til;            // T(i, l)
-        gstore<CO>(gTt + 256 * b + tid, til);
+        if (lw) {
+            TbT[lq + 16 * lj] = til;        // T(i, l)
+            gstore<CO>(gTt + 256 * b + tid, til);
+        }
         lds_barrier();
 #pragma unroll
         for (int o = 0; o < OWN; ++o)
@@ -612,7 +625,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[o][r], W2);
-                if (PAIR) store16<CO>(T1, 16 * b, 16 * (w + 4 * o), R1b[o] - W2);
+                if (PAIR) store16<CO>(T1, 16 * b, 16 * (w + 8 * o), R1b[o] - W2);
                 W[o] = W2;
             }
 #pragma unroll
@@ -653,10 +666,10 @@ template <int NB, int KIND, bool CO, bool HQ>
 __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
                                        int* sch) {
     constexpr int MT = NB / 16;
-    constexpr int NS = NB >= 64 ? 64 : NB;
+    constexpr int NS = NB;                   // the whole tile: one 16-column slice per wave
     constexpr int LDV = NB + 1;
     constexpr int BUF = 16 * LDV + 256;       // V_b (NB x 16, stride LDV) then T_b^T (16 x 16)
-    constexpr int PRE = NB / 16 + 1;          // staged doubles per thread and block
+    constexpr int PRE = 16 * NB / NT + 1;     // staged doubles per thread and block
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int c0 = part * NS + 16 * w;
@@ -667,20 +680,21 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
 
     // Block b of the record: V(:, 16b..16b+15) is contiguous (column-major),
-    // T_b^T follows the two nb x nb matrices.  Thread t stages elements t + 256k.
+    // T_b^T follows the nb x nb matrix.  Thread t stages elements t + NT k of
+    // V_b and element t of T_b^T (t < 256).
     auto fetch = [&](int b, double (&pre)[PRE]) {
 #pragma unroll
-        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
-        pre[PRE - 1] = rec.ld(8 * tid, 8 * (NB * NB + 256 * b));
+        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + NT * k), 8 * (16 * b * NB));
+        pre[PRE - 1] = tid < 256 ? rec.ld(8 * tid, 8 * (NB * NB + 256 * b)) : 0.0;
     };
     auto stage = [&](int buffer, const double (&pre)[PRE]) {
         double* buf = lds + buffer * BUF;
 #pragma unroll
         for (int k = 0; k < PRE - 1; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             buf[(e % NB) + (e / NB) * LDV] = pre[k];
         }
-        buf[16 * LDV + tid] = pre[PRE - 1];
+        if (tid < 256) buf[16 * LDV + tid] = pre[PRE - 1];
     };
     auto blk = [](int step) { return HQ ? MT - 1 - step : step; };
 
@@ -795,11 +809,11 @@ template <int NB, int KIND, bool CO, bool SPLIT>
 __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
                                          int* sch) {
     constexpr int MT = NB / 16;
-    constexpr int NS = NB >= 64 ? 64 : NB;
+    constexpr int NS = NB;                   // the whole tile: one 16-column slice per wave
     constexpr int LDV = NB + 1;
     constexpr int PL = 16 * LDV + 256;        // floats per plane: V_b (NB x 16) then T_b^T
     constexpr int BUF = (SPLIT ? 2 : 1) * PL; // hi plane [, lo plane]
-    constexpr int PRE = NB / 16 + 1;
+    constexpr int PRE = 16 * NB / NT + 1;
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int c0 = part * NS + 16 * w;
@@ -811,23 +825,25 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
 
     auto fetch = [&](int b, double (&pre)[PRE]) {
 #pragma unroll
-        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + 256 * k), 8 * (16 * b * NB));
-        pre[PRE - 1] = rec.ld(8 * tid, 8 * (NB * NB + 256 * b));
+        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + NT * k), 8 * (16 * b * NB));
+        pre[PRE - 1] = tid < 256 ? rec.ld(8 * tid, 8 * (NB * NB + 256 * b)) : 0.0;
     };
     auto stage = [&](int b, const double (&pre)[PRE]) {
         float* hi = fl + (b & 1) * BUF;
         float* lo = hi + PL;
 #pragma unroll
         for (int k = 0; k < PRE - 1; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             const int at = (e % NB) + (e / NB) * LDV;
             const float h = (float)pre[k];
             hi[at] = h;
             if (SPLIT) lo[at] = lo32(pre[k], h);
         }
-        const float h = (float)pre[PRE - 1];
-        hi[16 * LDV + tid] = h;
-        if (SPLIT) lo[16 * LDV + tid] = lo32(pre[PRE - 1], h);
+        if (tid < 256) {
+            const float h = (float)pre[PRE - 1];
+            hi[16 * LDV + tid] = h;
+            if (SPLIT) lo[16 * LDV + tid] = lo32(pre[PRE - 1], h);
+        }
     };
     // Product of a (16 x 4) A-fragment pair with a B-fragment given in FP64.
     auto prod = [&](float ah, float al, double bv, f4 acc) {

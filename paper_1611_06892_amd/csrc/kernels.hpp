@@ -39,8 +39,9 @@ struct KArgs {
                              // {ready-wait start, run start, run end, workgroup}
 };
 
-// Update strip width (columns of the logical C tile per work unit).
-inline int strip_width(int nb) { return nb >= 64 ? 64 : nb; }
+// Update strip width (columns of the logical C tile per work unit): the whole
+// tile, one 16-column slice per wave of the 512-thread workgroup.
+inline int strip_width(int nb) { return nb; }
 
 // One V/T record: V (nb x nb) and nb/16 blocks T_b^T (16 x 16).
 inline int64_t record_doubles(int nb) { return 1LL * nb * nb + 16LL * nb; }

@@ -44,12 +44,16 @@ def test_trace_respects_the_task_graph(bb, m, n, nb, tree, variant):
     tasks, off, idx = plan.export()
     nt = len(off) - 1
 
-    # Every (task, part) unit exactly once.
-    parts = np.array([1 if tasks[t, 0] <= 2 else (nb + min(nb, 64) - 1) // min(nb, 64) for t in range(nt)])
-    seen = {}
+    # Every task runs, each of its units (parts 0, 1, ...) exactly once, and a
+    # panel task is one unit.
+    parts = {}
     for t, p in zip(tr["task"], tr["part"]):
-        seen[(int(t), int(p))] = seen.get((int(t), int(p)), 0) + 1
-    assert len(seen) == int(parts.sum()) and all(c == 1 for c in seen.values())
+        parts.setdefault(int(t), []).append(int(p))
+    assert sorted(parts) == list(range(nt))
+    for t, ps in parts.items():
+        assert sorted(ps) == list(range(len(ps)))
+        if tasks[t, 0] <= 2:
+            assert ps == [0]
 
     # Times in order per unit; workgroups within the grid.
     assert np.all(tr["wait"] <= tr["start"]) and np.all(tr["start"] <= tr["end"])
