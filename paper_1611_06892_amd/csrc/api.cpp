@@ -90,8 +90,8 @@ const double kUnit[bb::NKINDS] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0, 6.0, 12.0, 6.0}
 // is flops, it reflects that a panel is a chain of nb dependent Householder
 // steps while an update is throughput-bound MFMA work (measured on MI355X for
 // nb = 128 in a loaded run: GEQRT / TSQRT / TTQRT panels ~100 / 135 / 120 us,
-// UNMQR / TSMQR / TTMQR strips ~25 / 37 / 32 us).
-const double kGpuCost[bb::NKINDS] = {10.0, 13.5, 12.0, 2.5, 3.7, 3.2, 2.5, 3.7, 3.2};
+// UNMQR / TSMQR / TTMQR tile updates ~41 / 60 / 53 us).
+const double kGpuCost[bb::NKINDS] = {10.0, 13.5, 12.0, 4.1, 6.0, 5.3, 4.1, 6.0, 5.3};
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
