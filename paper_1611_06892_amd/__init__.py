@@ -462,7 +462,9 @@ def pack_batch(mats, device="cuda"):
     import torch
     sizes = [int(A.shape[0]) * int(A.shape[1]) for A in mats]
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    buf = torch.empty(int(offsets[-1]) + 1, dtype=torch.float64, device=device)
+    # One spare element keeps the buffer non-empty; zeroed so that whole
+    # buffers compare equal across runs.
+    buf = torch.zeros(int(offsets[-1]) + 1, dtype=torch.float64, device=device)
     for A, o, sz in zip(mats, offsets, sizes):
         T = torch.as_tensor(A, dtype=torch.float64)
         buf[int(o):int(o) + sz].copy_(T.t().reshape(-1))
