@@ -105,3 +105,23 @@ def test_batch_reuse_and_timing(bb):
         assert plan.last_kernel_ms() > 0.0
         outs.append(buf.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", ["f64_upd_f32", "f64_upd_split32"])
+def test_mixed_precision_batch(bb, prec):
+    """Updates on FP32 matrix cores in a batch: every matrix within the FP32
+    backward-error bound 50 n eps32 ||A|| of the oracle (the single-matrix
+    precision tests use the same one), and bitwise equal to the same matrix
+    reduced alone in that mode."""
+    mats, nbs, trees, variants = mixed_batch(24, seed=17)
+    print("mixed-precision batch", prec, len(mats), flush=True)
+    plan, Bs = run_batch(bb, mats, nb=nbs, tree=trees, variant=variants, prec=prec)
+    for i, (A, B) in enumerate(zip(mats, Bs)):
+        n = A.shape[1]
+        assert oracle.band_violation(B, nbs[i]) == 0.0, i
+        Bo, _ = oracle.band_reduce(A, nbs[i])
+        d = np.linalg.norm(oracle.sign_normalize(B, nbs[i]) - oracle.sign_normalize(Bo, nbs[i]))
+        assert d <= 50 * n * 2.0 ** -24 * np.linalg.norm(A), (i, A.shape, d)
+    for i in (0, 13, 23):
+        Bsingle, _, _ = bb.band(torch.from_numpy(mats[i]), nbs[i], trees[i], variants[i], prec=prec)
+        assert np.array_equal(Bsingle.cpu().numpy(), Bs[i]), i
