@@ -40,7 +40,7 @@ template <int NB>
 struct Shape {
     static constexpr int MT = NB / 16;                 // 16 x 16 tiles per tile side
     static constexpr int LDL = NB + 1;                 // LDS stride of the leaf (odd: conflict-free)
-    static constexpr int PANEL = 16 * LDL + 2 * NB + 16 + 512;   // doubles used by a panel
+    static constexpr int PANEL = 16 * LDL + 2 * NB + 16 + 768;   // doubles used by a panel
     static constexpr int UPDATE = 2 * (16 * LDL + 256);           // ... and by an update
     static constexpr int LDS = PANEL > UPDATE ? PANEL : UPDATE;
 };
@@ -359,15 +359,15 @@ __device__ __forceinline__ void retire(const KArgs& a, Prev& p) {
 //
 // Columns are processed in blocks of 16 (the paper's inner blocking ib):
 //  1. leaf: the 16 columns of block b are factored one column at a time by
-//     all 256 threads (thread (c, q) holds rows q, q+16, ... of leaf column c
-//     in registers; one barrier per column).  The dot products of each new
+//     the 256 threads of waves 0-3 (thread (c, q) holds rows q, q+16, ... of
+//     leaf column c in registers; one barrier per column).  The dot products of each new
 //     reflector with the finished ones give G_b = U_b^T U_b, from which
 //     T_b (16 x 16 upper, Q_b = I - U_b T_b U_b^T) follows by the forward
 //     recurrence T(c,c) = tau_c, T(0:c-1,c) = -tau_c T(0:c-1,0:c-1) G(0:c-1,c).
 //  2. trailing: Q_b^T is applied to the column tiles right of the block with
 //     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W);
 //     T_b is formed on the vector units while the first product runs.
-//     Column tile J lives in registers of wave J % 4 for the whole kernel.
+//     Column tile J lives in registers of wave J % 8 for the whole kernel.
 // Record (FP64): V (nb x nb, column-major), then the nb/16 blocks T_b^T
 // (16 x 16 column-major) -- the same blocked compact-WY form the update
 // kernels apply.
@@ -385,6 +385,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     double* taus = vbuf + 2 * NB;           // 16
     double* Gs = taus + 16;                 // G(l, c) at l + 16 c
     double* TbT = Gs + 256;                 // T(k, i) at i + 16 k
+    double* R1s = TbT + 256;                // PAIR: R1(16b + lq, 16b + lj) of the next block, per leaf thread
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int lj = tid >> 4, lq = tid & 15; // leaf column, row phase
     const bool lw = tid < 256;              // waves 0-3 run the leaf and form T_b
@@ -399,6 +400,13 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 #pragma unroll
     for (int o = 0; o < OWN; ++o)
         if (w + 8 * o < MT) load_slice<MT>(TX, 16 * (w + 8 * o), xt[o]);
+    // R1's row block b is changed by no block before b (the reflectors of
+    // block b' touch rows of block b' only), so the diagonal entries the leaf
+    // of block b + 1 starts from are read during block b, before that block's
+    // stores: with one in-order counter for loads and stores, a load issued
+    // after the stores would also wait for them.  Each leaf thread keeps its
+    // own entry in LDS until it is needed.
+    if (PAIR && lw) R1s[tid] = T1.get(lq, lj);
     retire(a, prev);
 
     for (int b = 0; b < MT; ++b) {
@@ -422,7 +430,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         if (lw) {
 #pragma unroll
             for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
-            if (PAIR) r1 = T1.get(16 * b + lq, 16 * b + lj);
+            if (PAIR) r1 = R1s[tid];
         }
         // The column loop is instantiated per block index B, which fixes at
         // compile time where each register slot s (rows lq + 16 s) lies
@@ -540,6 +548,19 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             case 6: leaf(std::integral_constant<int, 6>{}); break;
             default: leaf(std::integral_constant<int, 7>{}); break;
         }
+        // Loads ahead of the leaf outputs' stores: the next block's diagonal
+        // entry of R1 and this block's rows of R1 in the trailing tiles.
+        double r1n = 0.0;
+        if (PAIR && lw && b + 1 < MT) r1n = T1.get(16 * (b + 1) + lq, 16 * (b + 1) + lj);
+        bool act[OWN];
+        d4 R1b[OWN], W[OWN];
+#pragma unroll
+        for (int o = 0; o < OWN; ++o) {
+            const int J = w + 8 * o;
+            act[o] = J < MT && J > b;
+            R1b[o] = d4{0.0, 0.0, 0.0, 0.0};
+            if (PAIR && act[o]) R1b[o] = load16(T1, 16 * b, 16 * J);
+        }
         // Leaf outputs, each thread on the leaf slots it read: explicit U_b
         // into the leaf buffer and the record, R (GEQRT) or zeros (TS/TT)
         // into the matrix.
@@ -556,6 +577,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 TX.put<CO>(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
             }
             if (PAIR) T1.put<CO>(16 * b + lq, 16 * b + lj, r1);
+            if (PAIR && b + 1 < MT) R1s[tid] = r1n;
         }
         lds_barrier();
 
@@ -564,16 +586,8 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         // units form T_b by the forward recurrence T(c,c) = tau_c,
         // T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c), thread (i, l) =
         // (tid/16, tid%16) holding T(i,l): one product and a row sum per column.
-        bool act[OWN];
-        d4 R1b[OWN], W[OWN];
 #pragma unroll
-        for (int o = 0; o < OWN; ++o) {
-            const int J = w + 8 * o;
-            act[o] = J < MT && J > b;
-            R1b[o] = d4{0.0, 0.0, 0.0, 0.0};
-            if (PAIR && act[o]) R1b[o] = load16(T1, 16 * b, 16 * J);
-            W[o] = R1b[o];
-        }
+        for (int o = 0; o < OWN; ++o) W[o] = R1b[o];
         double gl[16];
         if (lw) {
 #pragma unroll
