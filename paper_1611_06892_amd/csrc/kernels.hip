@@ -662,11 +662,11 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 }
 
 // ---------------------------------------------------------------------------
-// Update kernels: UNMQR, TSMQR, TTMQR (Table 1) on the logical column strip
-// [64 part, 64 part + 64) of the trailing tile(s) (32 columns when nb = 32).
-// Wave w owns the 16 columns 64 part + 16 w .. + 15 of C2 (and C1) and applies
-// the nb/16 blocks of the record in order (block b+1 is fetched from memory
-// while block b is applied, then staged in LDS for all four waves):
+// Update kernels: UNMQR, TSMQR, TTMQR (Table 1) on the whole trailing tile
+// (or tile pair).  Wave w owns the 16 logical columns 16 w .. 16 w + 15 of C2
+// (and C1); waves past the tile's width only stage and synchronize.  Each
+// applies the nb/16 blocks of the record in order (block b+1 is fetched from
+// memory while block b is applied, then staged in LDS for all eight waves):
 //   W = C1(block-row b) + V_b^T C2     (UNMQR: no C1)
 //   W = T_b^T W
 //   C1(block-row b) -= W,   C2 -= V_b W
