@@ -198,7 +198,7 @@ def bench_adjoint(args, bb, torch, np, workloads):
     A = workloads.gaussian(m, n, cfg["seed"])
     W = torch.as_tensor(workloads.band_weights(n, nb, cfg["wseed"])).cuda()
     S0 = bb.to_colmajor(torch.from_numpy(A))
-    plan = bb.Plan(m, n, nb, args.tree, "rbidiag")
+    plan = bb.Plan(m, n, nb, args.tree, "rbidiag", prec=args.prec)
     vt, ws = plan.alloc()
     aws = torch.empty(plan.adjoint_workspace(), dtype=torch.uint8, device="cuda")
     S = torch.empty_like(S0)
@@ -221,15 +221,48 @@ def bench_adjoint(args, bb, torch, np, workloads):
     st = bb.poll_error(ws)
     if st != 0:
         raise RuntimeError("device scheduler error %d" % st)
-    # accuracy: central differences of the forward in 4 random unit directions
-    Wd = W
+    Ag = Ab.cpu().numpy()
+    check = {}
+    if args.prec != "f64":
+        # mixed forward: distance to the gradient of the FP64 forward (central
+        # differences of a forward with FP32 rounding would measure its noise)
+        p64 = bb.Plan(m, n, nb, args.tree, "rbidiag")
+        v64, w64 = p64.alloc()
+        S.copy_(S0)
+        p64.execute(S, m, v64, w64)
+        A64 = p64.adjoint(S, m, W, v64).cpu().numpy()
+        check["rel_diff_to_f64_gradient"] = float(np.linalg.norm(Ag - A64) / np.linalg.norm(A64))
+        del p64, v64, w64
+    else:
+        check["fd_max_err_rel_grad_norm"] = fd_check(A, Ag, W, plan, bb, torch, np, m, n)
+    f_ms, b_ms = float(np.median(fw)), float(np.median(bw))
+    flops = workloads.flops_bidiag(m, n)
+    dtype = {"f64": "f64", "f64_upd_f32": "f64 panels, f32 updates; f64 adjoint",
+             "f64_upd_split32": "f64 panels, split-f32 updates; f64 adjoint"}[args.prec]
+    out = {
+        "metric": METRIC, "value": round(flops / ((f_ms + b_ms) * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f_ms + b_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": "adjoint 8192x1024 nb=128 rbidiag %s, forward + gradient of "
+                               "sum(W*B)" % args.tree, "m": m, "n": n, "nb": nb, "prec": args.prec,
+                   "parallelism": "single GPU"},
+        "forward_ms": round(f_ms, 3), "adjoint_ms": round(b_ms, 3),
+        "adjoint_over_forward": round(b_ms / f_ms, 3),
+        "check": check,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def fd_check(A, Ag, W, plan, bb, torch, np, m, n):
+    """Central differences of the forward in 4 random unit directions: the
+    largest error relative to the gradient's norm."""
     def L(M):
         Sm = bb.to_colmajor(torch.from_numpy(M))
-        p2 = plan
-        v2, w2 = p2.alloc()
-        p2.execute(Sm, m, v2, w2)
-        return float(torch.sum(Wd * Sm.t()[:n]))
-    Ag = Ab.cpu().numpy()
+        v2, w2 = plan.alloc()
+        plan.execute(Sm, m, v2, w2)
+        return float(torch.sum(W * Sm.t()[:n]))
     rng = np.random.default_rng(8)
     h = 1e-6 * np.linalg.norm(A)
     fd_err = 0.0
@@ -238,22 +271,7 @@ def bench_adjoint(args, bb, torch, np, workloads):
         E /= np.linalg.norm(E)
         fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
         fd_err = max(fd_err, abs(fd - float(np.sum(Ag * E))) / np.linalg.norm(Ag))
-    f_ms, b_ms = float(np.median(fw)), float(np.median(bw))
-    flops = workloads.flops_bidiag(m, n)
-    out = {
-        "metric": METRIC, "value": round(flops / ((f_ms + b_ms) * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f_ms + b_ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "adjoint 8192x1024 nb=128 rbidiag %s, forward + gradient of "
-                               "sum(W*B)" % args.tree, "m": m, "n": n, "nb": nb,
-                   "parallelism": "single GPU"},
-        "forward_ms": round(f_ms, 3), "adjoint_ms": round(b_ms, 3),
-        "adjoint_over_forward": round(b_ms / f_ms, 3),
-        "check": {"fd_max_err_rel_grad_norm": fd_err},
-        "roofline": None, "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+    return fd_err
 
 
 def main():

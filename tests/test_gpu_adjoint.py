@@ -90,6 +90,45 @@ def test_adjoint_finite_differences(bb, m, n, nb, tree, variant):
         assert abs(fd - an) <= 1e-6 * max(1.0, np.linalg.norm(Ag)), (fd, an)
 
 
+def block_condition(B, n, nb):
+    """Largest 2-norm condition number of the diagonal and super-diagonal
+    nb-blocks of the band B (the blocks the reverse sweep solves with)."""
+    kappa = 1.0
+    for k0 in range(0, n, nb):
+        k1 = min(k0 + nb, n)
+        kappa = max(kappa, np.linalg.cond(B[k0:k1, k0:k1]))
+        if k1 < n:
+            kappa = max(kappa, np.linalg.cond(B[k0:k1, k1:min(k1 + nb, n)]))
+    return kappa
+
+
+@pytest.mark.parametrize("prec", ["f64_upd_f32", "f64_upd_split32"])
+@pytest.mark.parametrize("m,n,nb,tree,variant", [CASES[0], CASES[3]])
+def test_adjoint_of_mixed_precision_forward(bb, prec, m, n, nb, tree, variant):
+    """Forward with FP32 (or split-FP32) updates, adjoint in FP64 from its
+    records.  The mixed forward reduces A + dA exactly with ||dA|| within
+    50 n eps32 ||A|| (the bound of the mixed-precision band tests), and the
+    reverse sweep solves with the diagonal and super-diagonal blocks of B, so
+    the gradient of the reference moves by at most that relative amount times
+    the blocks' largest condition number."""
+    from oracle import adjoint as ref
+    print("case", prec, m, n, nb, tree, variant, flush=True)
+    A = workloads.gaussian(m, n, seed=700 + m + n + nb)
+    W = band_weights(n, nb, seed=n + 2)
+    plan = bb.Plan(m, n, nb, tree, variant, prec=prec, watchdog_s=20.0)
+    S = torch.as_tensor(A).cuda().t().contiguous()
+    vt, ws = plan.alloc()
+    plan.execute(S, m, vt, ws)
+    assert bb.poll_error(ws) == 0
+    Ag = plan.adjoint(S, m, torch.as_tensor(W), vt).cpu().numpy()
+    B = S.t().cpu().numpy()
+    _, Aref = ref.band_loss_gradient(A, W, nb, B)
+    rel = np.linalg.norm(Ag - Aref) / np.linalg.norm(Aref)
+    kappa = block_condition(B, n, nb)
+    print("relative difference", rel, "block condition", kappa, flush=True)
+    assert rel <= 50 * n * 2.0 ** -24 * kappa
+
+
 def test_autograd_function(bb):
     m, n, nb = 300, 192, 64
     A = torch.as_tensor(workloads.gaussian(m, n, seed=3)).cuda().requires_grad_(True)
