@@ -366,7 +366,7 @@ __device__ __forceinline__ void retire(const KArgs& a, Prev& p) {
 //     recurrence T(c,c) = tau_c, T(0:c-1,c) = -tau_c T(0:c-1,0:c-1) G(0:c-1,c).
 //  2. trailing: Q_b^T is applied to the column tiles right of the block with
 //     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W);
-//     T_b is formed on the vector units while the first product runs.
+//     T_b is formed by waves 4-7 during the leaf, one column behind it.
 //     Column tile J lives in registers of wave J % 8 for the whole kernel.
 // Record (FP64): V (nb x nb, column-major), then the nb/16 blocks T_b^T
 // (16 x 16 column-major) -- the same blocked compact-WY form the update
@@ -427,6 +427,19 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         // 1. Leaf.
         double x[SR];
         double r1 = 0.0;                    // PAIR: R1(16b + lq, 16b + lj)
+        // Waves 4-7, idle in the leaf, form T_b meanwhile by the forward
+        // recurrence T(c,c) = tau_c, T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c):
+        // thread (i, l) = (tid/16 - 16, tid%16) holds T(i, l), and column c
+        // is formed once G(:, c) is complete, one column behind the leaf.
+        double til = 0.0;
+        auto tstep = [&](int cc) {
+            const int ti = lj - 16;
+            const double tcv = taus[cc];
+            const double gv = Gs[lq + 16 * cc];
+            const double sm = sum16((lq >= ti && lq < cc) ? til * gv : 0.0);
+            const double tic = cc < ti ? 0.0 : (cc == ti ? tcv : -tcv * sm);
+            if (lq == cc) til = tic;
+        };
         if (lw) {
 #pragma unroll
             for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
@@ -505,7 +518,10 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                         if (lq == 0) taus[c] = tau;
                     }
                     lds_barrier();
-                    if (lw) {
+                    if (!lw) {
+                        // G(:, c-1) was completed before this barrier
+                        if (c > 0) tstep(c - 1);
+                    } else {
                         // the reflector and tau_c are read together (one LDS latency)
                         const double tc = taus[c];
                         double vv[SR];
@@ -581,20 +597,10 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
         }
         lds_barrier();
 
-        // 2. Trailing update of the column tiles right of block b.  The
-        // products W = R1 + U_b^T X run on the matrix cores while the vector
-        // units form T_b by the forward recurrence T(c,c) = tau_c,
-        // T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c), thread (i, l) =
-        // (tid/16, tid%16) holding T(i,l): one product and a row sum per column.
+        // 2. Trailing update of the column tiles right of block b:
+        // W = R1 + U_b^T X, then W = T_b^T W, then X -= U_b W.
 #pragma unroll
         for (int o = 0; o < OWN; ++o) W[o] = R1b[o];
-        double gl[16];
-        if (lw) {
-#pragma unroll
-            for (int c = 0; c < 16; ++c) gl[c] = Gs[lq + 16 * c];
-        }
-        double til = 0.0;
-        constexpr int TSTEP = 16 / MT;      // recurrence columns per 16-row step
         double la[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) la[r] = Lf[(4 * r + g) + j * LDL];
@@ -612,25 +618,16 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 #pragma unroll
                     for (int r = 0; r < 4; ++r) W[o] = mfma(la[r], xt[o][i][r], W[o]);
                 }
-            if (lw) {
-#pragma unroll
-                for (int u = 0; u < TSTEP; ++u) {
-                    const int c = TSTEP * i + u;
-                    const double tcv = taus[c];
-                    const double sm = sum16((lq >= lj && lq < c) ? til * gl[c] : 0.0);
-                    const double tic = c < lj ? 0.0 : (c == lj ? tcv : -tcv * sm);
-                    if (lq == c) til = tic;
-                }
-            }
             SCHED_FENCE();
             if (i + 1 < MT) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) la[r] = ln[r];
             }
         }
-        if (lw) {
-            TbT[lq + 16 * lj] = til;        // T(i, l)
-            gstore<CO>(gTt + 256 * b + tid, til);
+        if (!lw) {
+            tstep(15);
+            TbT[lq + 16 * (lj - 16)] = til;     // T(i, l)
+            gstore<CO>(gTt + 256 * b + (tid - 256), til);
         }
         lds_barrier();
 #pragma unroll
