@@ -245,3 +245,80 @@ def test_reference_gradient_matches_finite_differences(m, n, nb):
         fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
         an = float(np.sum(G * E))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def _exact_band(m, n, nb, seed):
+    """An m x n matrix with random nonzero entries exactly on 0 <= j - i <= nb
+    (rows >= n zero), the band form of Section 3.4, built entry by entry."""
+    rng = np.random.default_rng(seed)
+    B = np.zeros((m, n))
+    for i in range(min(m, n)):
+        for j in range(i, min(n, i + nb + 1)):
+            B[i, j] = rng.uniform(1.0, 2.0) * rng.choice([-1.0, 1.0])
+    return B
+
+
+@pytest.mark.parametrize("m,n,nb", [(12, 9, 3), (9, 9, 1), (20, 7, 4)])
+def test_band_violation_detects_each_outside_entry(m, n, nb):
+    """band_violation must report exactly the one planted entry for every
+    position outside the band (below the diagonal, beyond the band edge, in
+    the rows >= n) and nothing for every position inside it (the diagonal and
+    the band edge j - i = nb included)."""
+    B = _exact_band(m, n, nb, seed=m + n + nb)
+    assert oracle.band_violation(B, nb) == 0.0
+    for i in range(m):
+        for j in range(n):
+            inside = i < n and 0 <= j - i <= nb
+            C = B.copy()
+            C[i, j] = 1e-300 if inside else 0.0
+            if inside:
+                assert oracle.band_violation(C, nb) == 0.0, (i, j)
+                continue
+            for v in (3.5, -0.25, 5e-324):
+                C[i, j] = v
+                assert oracle.band_violation(C, nb) == abs(v), (i, j, v)
+
+
+def test_band_violation_named_positions():
+    """The three positions a lax mask would miss: the subdiagonal (i, i-1),
+    one past the band edge (i, i+nb+1) and a row below the n x n block."""
+    m, n, nb = 10, 6, 2
+    B = _exact_band(m, n, nb, seed=3)
+    for (i, j), v in [((3, 2), 0.75), ((1, 1 + nb + 1), -2.0), ((n, 0), 1.25),
+                      ((m - 1, n - 1), 4.0), ((n, n - 1), -3.0)]:
+        C = B.copy()
+        C[i, j] = v
+        assert oracle.band_violation(C, nb) == abs(v)
+
+
+@pytest.mark.parametrize("which", ["q", "p", "b"])
+def test_invariants_reject_a_perturbed_factor(which):
+    """invariants() must exceed the 50 n eps bound when one column of Q or P
+    (or one band entry of B) is perturbed by far more than rounding: both the
+    orthogonality and the residual measures see a column change."""
+    m, n, nb = 30, 18, 4
+    A = workloads.gaussian(m, n, seed=21)
+    B, refl = oracle.band_reduce(A, nb)
+    Q, P = oracle.form_q(refl), oracle.form_p(refl)
+    tol = 50 * n * EPS
+    base = oracle.invariants(A, B, Q, P)
+    assert max(base.values()) <= tol
+    rng = np.random.default_rng(5)
+    if which == "q":
+        Q = Q.copy()
+        Q[:, 7] += 1e-9 * rng.standard_normal(m)
+        inv = oracle.invariants(A, B, Q, P)
+        assert inv["orth_q"] > tol and inv["residual"] > tol
+        assert inv["orth_p"] <= tol
+    elif which == "p":
+        P = P.copy()
+        P[:, 11] += 1e-9 * rng.standard_normal(n)
+        inv = oracle.invariants(A, B, Q, P)
+        assert inv["orth_p"] > tol and inv["residual"] > tol
+        assert inv["orth_q"] <= tol
+    else:
+        B = B.copy()
+        B[5, 5 + nb] *= 1 + 1e-9
+        inv = oracle.invariants(A, B, Q, P)
+        assert inv["residual"] > tol
+        assert inv["orth_q"] <= tol and inv["orth_p"] <= tol
