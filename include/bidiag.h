@@ -20,18 +20,27 @@
  *     lda >= max(1, m).  m and n need not be multiples of nb: the last tile
  *     row/column is handled as if zero-padded (padding is never read or
  *     written in memory).
- *   - All device buffers are owned by the caller.  The library never frees or
- *     retains them past the call.  A plan owns a small device copy of its task
- *     graph (allocated at the plan's first execution on a device, freed by
- *     bb_plan_destroy).
+ *   - All device memory is owned by the caller: matrices, V/T records and
+ *     the workspace.  The library allocates no device memory, never frees or
+ *     retains a caller's pointer past the call, and keeps no device state
+ *     between calls.  A plan owns host memory only: its task graph and a copy
+ *     of what the device reads of it (page-locked when a device is present),
+ *     which every execution copies into the workspace with an asynchronous
+ *     copy on the caller's stream.
  *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL means
  *     the default stream) and is asynchronous: results are valid once the
- *     stream has reached the enqueued work.
+ *     stream has reached the enqueued work.  No entry point that enqueues
+ *     work waits for the device, except the bb_*poll_error and
+ *     bb_*last_kernel_ms queries, which say so.
  *   - Return codes: BB_OK (0); -i when argument i (1-based) is invalid, in the
  *     LAPACK convention; a positive BB_E* code for runtime errors.  No C++
  *     exception crosses the ABI.
- *   - Reentrancy: calls with distinct plans and buffers may run concurrently;
- *     one plan's executions must not overlap on the same workspace.
+ *   - Reentrancy: calls with distinct buffers may run concurrently from
+ *     several host threads, also with the same plan (an execution only reads
+ *     its plan); executions that overlap on one workspace race.  Destroying a
+ *     plan waits for the devices it uploaded on (its host copy may still be
+ *     the source of an enqueued copy), so it must not race with executions
+ *     of that plan.
  */
 #ifndef BIDIAG_H
 #define BIDIAG_H
@@ -106,8 +115,9 @@ typedef struct {
 } bb_plan_stats;
 
 /*
- * bb_plan_create -- build the task graph of one reduction (host only, no GPU
- * call).  Arguments: out plan (1), m (2), n (3) with m >= n >= 1, nb (4) in
+ * bb_plan_create -- build the task graph of one reduction (host work only: no
+ * device memory and no device work; the host copy of the graph is
+ * page-locked when a device is present).  Arguments: out plan (1), m (2), n (3) with m >= n >= 1, nb (4) in
  * {32, 64, 128}, tree (5) BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64*,
  * opts (8, may be NULL for defaults).  The plan is independent of the data and
  * of lda; it can be executed any number of times.
@@ -115,7 +125,8 @@ typedef struct {
 int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int variant,
                    int prec, const bb_opts* opts);
 
-/* Release a plan and its device copy of the task graph. NULL is ignored. */
+/* Release a plan (after synchronizing the devices it uploaded its graph on).
+ * NULL is ignored. */
 void bb_plan_destroy(bb_plan* plan);
 
 /*
@@ -127,7 +138,11 @@ void bb_plan_destroy(bb_plan* plan);
  *              upper triangular (compact WY form blocked by 16 columns).
  *              Kept after the call (Q and P are the products of these records
  *              in task order).
- *   ws_bytes : scheduler state (dependency counters, ticket, error flag).
+ *   ws_bytes : scheduler state (error flag, ticket and done counters, one
+ *              dependency counter per task, the optional trace) followed by
+ *              the copy of the task graph that each execution uploads
+ *              (tasks, successor lists, unit order).  Contents are not kept
+ *              between executions.
  */
 int bb_plan_workspace(const bb_plan* plan, size_t* vt_bytes, size_t* ws_bytes);
 
@@ -155,7 +170,10 @@ int bb_execute(bb_plan* plan, void* A, int64_t lda, void* vt, size_t vt_bytes, v
 
 /*
  * bidiag_band -- one-shot form of bb_plan_create + bb_execute with a plan
- * cached inside the library by (m, n, nb, tree, variant, prec, opts).
+ * cached inside the library by (m, n, nb, tree, variant, prec, opts).  The
+ * cache holds at most 16 plans (least recently used out first; bb_query
+ * fills it too) and bb_cache_clear empties it; a plan in use by another
+ * thread's call is released when that call returns.
  * Argument numbering: A (1), m (2), n (3), lda (4), nb (5), tree (6),
  * variant (7), prec (8), vt (9), vt_bytes (10), ws (11), ws_bytes (12),
  * opts (13), stream (14).
@@ -164,7 +182,7 @@ int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, in
                 int prec, void* vt, size_t vt_bytes, void* ws, size_t ws_bytes,
                 const bb_opts* opts, void* stream);
 
-/* Workspace sizes for bidiag_band with the same arguments. */
+/* Workspace sizes for bidiag_band with the same arguments (caches the plan). */
 int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
              size_t* vt_bytes, size_t* ws_bytes);
 
@@ -191,8 +209,9 @@ int bb_plan_trace(bb_plan* plan, size_t* offset, int64_t* nunits, double* tick_h
  * place; ncols (7) >= 0 (0: nothing is done); ws (8) with ws_bytes (9) >=
  * bb_apply_workspace's size (scheduler state, contents not kept); stream
  * (10).  Runs on FP64 matrix cores whatever the plan's prec.  The plan keeps
- * one host/device task graph per (side, transpose, ceil(ncols/nb)); a plan
- * must not be used from several host threads at once for these calls.
+ * one host task graph per (side, transpose, ceil(ncols/nb)), built on first
+ * use (normally by bb_apply_workspace) under a lock; that graph is uploaded
+ * into ws like the reduction's.
  */
 int bb_apply_q(bb_plan* plan, int transpose, const void* vt, size_t vt_bytes, void* C,
                int64_t ldc, int64_t ncols, void* ws, size_t ws_bytes, void* stream);
@@ -223,6 +242,12 @@ int bidiag_band_adjoint(bb_plan* plan, const void* B, int64_t ldb, const void* W
                         const void* vt, size_t vt_bytes, void* Abar, int64_t ldabar, void* ws,
                         size_t ws_bytes, void* stream);
 int bb_adjoint_workspace(bb_plan* plan, size_t* ws_bytes);
+
+/* Scheduler status of the last bidiag_band_adjoint on workspace ws (its
+ * applications of P and Q run the persistent scheduler): synchronizes
+ * `stream`, then *device_status = 0 or a BB_E* code, as bb_poll_error.
+ * Arguments: plan (1), ws (2), stream (3), device_status (4). */
+int bb_adjoint_poll_error(bb_plan* plan, const void* ws, void* stream, int* device_status);
 
 /* ---- batches of independent reductions ------------------------------- */
 /*
@@ -292,7 +317,8 @@ int bb_query_batched(int64_t count, const int64_t* m, const int64_t* n, const in
 
 /*
  * bidiag_band_batched -- one-shot bb_batch_create + bb_batch_execute with the
- * batch plan cached inside the library by its arguments.  Numbering: A (1),
+ * batch plan cached inside the library by its arguments (at most 4 batch
+ * plans, least recently used out first; bb_cache_clear empties the cache).  Numbering: A (1),
  * lda (2) (device arrays), count (3), m (4), n (5), nb (6), tree (7),
  * variant (8) (host arrays), prec (9), vt (10), vt_bytes (11), ws (12),
  * ws_bytes (13), opts (14), stream (15).
@@ -342,6 +368,11 @@ int bb_plan_auto_domains(const bb_plan* plan, int32_t* a, int64_t* nsteps);
  */
 double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int workgroups,
                         double gamma);
+
+/* Drop every plan the one-shot entry points cache (bidiag_band, bb_query,
+ * bidiag_band_batched).  Plans in use by a running call are released when
+ * that call returns. */
+void bb_cache_clear(void);
 
 const char* bb_strerror(int code);
 

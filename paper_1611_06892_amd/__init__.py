@@ -58,7 +58,7 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_tuned_config", "bb_batch_create", "bb_batch_destroy", "bb_batch_workspace",
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
-           "bb_adjoint_workspace", "bb_plan_trace"]
+           "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear"]
 
 
 def lib():
@@ -137,12 +137,30 @@ def lib():
     L.bidiag_band_adjoint.restype = i32
     L.bb_adjoint_workspace.argtypes = [P, szp]
     L.bb_adjoint_workspace.restype = i32
+    L.bb_adjoint_poll_error.argtypes = [P, vp, vp, ip]
+    L.bb_adjoint_poll_error.restype = i32
+    L.bb_cache_clear.argtypes = []
+    L.bb_cache_clear.restype = None
     L.bb_plan_trace.argtypes = [P, szp, lp, ctypes.POINTER(ctypes.c_double), vp]
     L.bb_plan_trace.restype = i32
     L.bb_strerror.argtypes = [i32]
     L.bb_strerror.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def query(m, n, nb, tree="auto", variant="bidiag", prec="f64", **opts):
+    """(vt_bytes, ws_bytes) for bidiag_band with these arguments (bb_query)."""
+    o = make_opts(**opts)
+    vt, ws = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().bb_query(int(m), int(n), int(nb), TREES[tree], VARIANTS[variant], PRECS[prec],
+                          ctypes.byref(o), ctypes.byref(vt), ctypes.byref(ws)), "bb_query")
+    return vt.value, ws.value
+
+
+def cache_clear():
+    """Drop the plans the one-shot entry points cache."""
+    lib().bb_cache_clear()
 
 
 def strerror(code: int) -> str:
@@ -309,11 +327,20 @@ class Plan:
         _check(lib().bb_adjoint_workspace(self._h, ctypes.byref(ws)), "bb_adjoint_workspace")
         return ws.value
 
-    def adjoint(self, Bcm, ldb, W, vt, ws=None, stream=None):
+    def adjoint_poll_error(self, ws, stream=None) -> int:
+        """Scheduler status of the last adjoint on ws (synchronizes the stream)."""
+        st = ctypes.c_int()
+        _check(lib().bb_adjoint_poll_error(self._h, ctypes.c_void_p(ws.data_ptr()),
+                                           _stream_handle(stream), ctypes.byref(st)),
+               "bb_adjoint_poll_error")
+        return st.value
+
+    def adjoint(self, Bcm, ldb, W, vt, ws=None, stream=None, check=False):
         """Gradient of sum(W * B) over the band with respect to the reduced
         matrix: Bcm is the column-major storage of the reduction's output B
         (leading dimension ldb), W an n x n tensor (only its band entries are
-        used).  Returns the m x n gradient (a CUDA tensor view)."""
+        used).  Returns the m x n gradient (a CUDA tensor view).  check=True
+        waits for the result and raises BidiagError on a scheduler error."""
         import torch
         Wcm = W.to(device=Bcm.device, dtype=torch.float64).t().contiguous()
         Ab = torch.empty(self.n, self.m, dtype=torch.float64, device=Bcm.device)
@@ -325,6 +352,10 @@ class Plan:
                                          ctypes.c_void_p(Ab.data_ptr()), self.m,
                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                          _stream_handle(stream)), "bidiag_band_adjoint")
+        if check:
+            st = self.adjoint_poll_error(ws, stream)
+            if st != 0:
+                raise BidiagError(st, "device scheduler (adjoint)")
         return Ab.t()
 
 
@@ -496,13 +527,16 @@ def _band_function():
             S = to_colmajor(A.detach())
             vt, ws = plan.alloc(S.device)
             plan.execute(S, m, vt, ws)
+            st = poll_error(ws)
+            if st != 0:
+                raise BidiagError(st, "device scheduler")
             ctx.plan, ctx.vt, ctx.S = plan, vt, S
             return S.t().clone()
 
         @staticmethod
         def backward(ctx, Bbar):
             n = ctx.plan.n
-            Ab = ctx.plan.adjoint(ctx.S, ctx.plan.m, Bbar[:n, :n], ctx.vt)
+            Ab = ctx.plan.adjoint(ctx.S, ctx.plan.m, Bbar[:n, :n], ctx.vt, check=True)
             return Ab.to(Bbar.dtype), None, None, None
 
     return BandBidiag

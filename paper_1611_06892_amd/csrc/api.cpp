@@ -1,18 +1,25 @@
 // C ABI of libbidiag (declarations and contracts in include/bidiag.h).
 //
-// A plan holds the task graph of one (m, n, nb, tree, variant) reduction, the
-// execution order of its work units and a lazily uploaded device copy of all
-// of it.  Execution enqueues either one persistent scheduler launch or one
-// launch per topological level on the caller's stream.
+// A plan holds the task graph of one (m, n, nb, tree, variant) reduction and
+// the execution order of its work units, built on the host at creation, with
+// a host copy of everything the device reads (page-locked when a device is
+// present).  Execution copies that graph into the caller's workspace with an
+// asynchronous copy on the caller's stream and enqueues either one persistent
+// scheduler launch or one launch per topological level after it: the library
+// allocates no device memory and keeps no device state between calls.
 #include "../../include/bidiag.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <queue>
@@ -22,6 +29,47 @@
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+
+namespace {
+
+// Host bytes that a launch copies into the caller's workspace.  Page-locked
+// when a device is present, so that the copy is an asynchronous DMA on the
+// caller's stream; plain memory on a host without one (plans are also built
+// and inspected there).
+struct HostBlob {
+    char* p = nullptr;
+    size_t bytes = 0;
+    bool pinned = false;
+    HostBlob() = default;
+    HostBlob(const HostBlob&) = delete;
+    HostBlob& operator=(const HostBlob&) = delete;
+    bool alloc(size_t b) {
+        release();
+        bytes = b;
+        const size_t n = std::max<size_t>(b, 8);
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 &&
+            hipHostMalloc((void**)&p, n, hipHostMallocDefault) == hipSuccess) {
+            pinned = true;
+        } else {
+            (void)hipGetLastError();
+            p = (char*)std::malloc(n);
+            pinned = false;
+        }
+        if (p) std::memset(p, 0, n);
+        return p != nullptr;
+    }
+    void release() {
+        if (!p) return;
+        if (pinned) (void)hipHostFree(p);
+        else std::free(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    ~HostBlob() { release(); }
+};
+
+}  // namespace
 
 struct bb_plan {
     int64_t m = 0, n = 0;
@@ -37,24 +85,25 @@ struct bb_plan {
     std::vector<int32_t> units_level;        // (task, part) pairs sorted by level
     std::vector<int32_t> level_off;          // units_level offsets per level
     double cp = 0.0, total = 0.0;
-    // device copy of the graph and schedule
-    int device = -1;
-    void* dblob = nullptr;
-    size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_ut = 0, off_ul = 0;
+    // Host copy of the graph the device reads, uploaded into the workspace
+    // by every execution: tasks, initial dependency counts, successors, the
+    // unit order of the chosen schedule, batched descriptors' sources.
+    HostBlob blob;
+    size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_units = 0;
     size_t off_gidx = 0, off_dims = 0;
-    size_t off_up = 0;
-    int cu_count = 0;
-    double wallclock_khz = 0.0;
+    std::atomic<uint32_t> used_devices{0};   // devices an upload was enqueued on (bit mask)
+    std::once_flag ev_once;
+    hipError_t ev_err = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool timed = false;
+    std::atomic<bool> timed{false};
     // Plans that apply Q, Q^T, P or P^T with this plan's records, by
     // (side, transpose, tile columns of C).
     std::map<std::tuple<int, int, int64_t>, bb_plan*> apply;
     std::mutex apply_mu;
-    // adjoint: operation list and its device copy
+    // adjoint: operation list and its host copy
+    std::mutex adj_mu;
     bbk::AdjointOps* adj = nullptr;
-    void* adj_dev = nullptr;
-    int adj_device = -1;
+    HostBlob adj_blob;
 };
 
 // A batch: one plan (union graph) per tile size, run one after the other.
@@ -73,8 +122,10 @@ struct bb_batch {
     std::vector<int64_t> rec_off;        // per matrix: byte offset of its first record in vt
     std::vector<int64_t> nrec;           // per matrix: number of records
     size_t vt_bytes = 0, ws_bytes = 0;
+    std::once_flag ev_once;
+    hipError_t ev_err = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool timed = false;
+    std::atomic<bool> timed{false};
     ~bb_batch();
 };
 
@@ -227,8 +278,8 @@ int build_schedule(bb_plan& P) {
     return validate(P) ? BB_OK : BB_EDAG;
 }
 
-// Workspace: control words, the launch's matrix descriptors, then one
-// dependency counter per task.
+// Workspace: control words, the launch's matrix descriptors, one dependency
+// counter per task, the trace (BB_FLAG_TRACE), then the copy of the graph.
 size_t ws_mats_off() { return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256); }
 size_t ws_deps_off(const bb_plan& P) {
     return ws_mats_off() + round_up(sizeof(bbk::MatDesc) * (size_t)P.nmats, 256);
@@ -236,83 +287,85 @@ size_t ws_deps_off(const bb_plan& P) {
 size_t ws_trace_off(const bb_plan& P) {
     return ws_deps_off(P) + round_up(sizeof(int32_t) * P.g.tasks.size(), 256);
 }
-size_t ws_bytes_of(const bb_plan& P) {
+size_t ws_blob_off(const bb_plan& P) {
     size_t b = ws_trace_off(P);
     if (P.opts.flags & BB_FLAG_TRACE) b += round_up(4 * sizeof(int64_t) * (P.units_ticket.size() / 2), 256);
     return b;
 }
+size_t ws_bytes_of(const bb_plan& P) { return ws_blob_off(P) + round_up(P.blob.bytes, 256); }
 
 size_t vt_bytes_of(const bb_plan& P) {
     return (size_t)P.g.nslots * (size_t)bbk::record_doubles(P.nb) * sizeof(double);
 }
 
-// Upload the graph and schedule to the current device (once per plan).
-int ensure_device(bb_plan& P) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
-    if (P.dblob && P.device == dev) return BB_OK;
-    if (P.dblob) {
-        (void)hipFree(P.dblob);
-        P.dblob = nullptr;
-    }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BB_EHIP;
-    P.cu_count = prop.multiProcessorCount;
-    int khz = 0;
-    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
-        khz = 100000;
-    P.wallclock_khz = (double)khz;
-
+// Lay out the device's view of the graph in the plan's host blob: tasks,
+// initial dependency counts, successor lists, the units of the plan's
+// schedule (priority order or levels) and, for batches, the per-matrix
+// sources of the descriptors.  Called once, when the plan is built.
+int build_blob(bb_plan& P) {
     const size_t nt = P.g.tasks.size();
-    std::vector<bbk::DevTask> dt(nt);
-    for (size_t t = 0; t < nt; ++t) {
-        const bb::Task& s = P.g.tasks[t];
-        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
-    }
+    const std::vector<int32_t>& units = P.opts.sched == BB_SCHED_PERSISTENT ? P.units_prio : P.units_level;
     size_t off = 0;
     P.off_tasks = off; off = round_up(off + nt * sizeof(bbk::DevTask), 256);
     P.off_ndeps = off; off = round_up(off + nt * 4, 256);
     P.off_succ_off = off; off = round_up(off + P.succ_off.size() * 4, 256);
     P.off_succ_idx = off; off = round_up(off + std::max<size_t>(1, P.succ_idx.size()) * 4, 256);
-    P.off_ut = off; off = round_up(off + P.units_ticket.size() * 4, 256);
-    P.off_ul = off; off = round_up(off + P.units_level.size() * 4, 256);
-    P.off_up = off; off = round_up(off + P.units_prio.size() * 4, 256);
+    P.off_units = off; off = round_up(off + units.size() * 4, 256);
     P.off_gidx = off; off = round_up(off + P.gidx.size() * 8, 256);
     P.off_dims = off; off = round_up(off + P.dims.size() * 8, 256);
-    std::vector<char> host(off, 0);
-    std::memcpy(host.data() + P.off_tasks, dt.data(), nt * sizeof(bbk::DevTask));
-    std::memcpy(host.data() + P.off_ndeps, P.ndeps.data(), nt * 4);
-    std::memcpy(host.data() + P.off_succ_off, P.succ_off.data(), P.succ_off.size() * 4);
-    if (!P.succ_idx.empty()) std::memcpy(host.data() + P.off_succ_idx, P.succ_idx.data(), P.succ_idx.size() * 4);
-    std::memcpy(host.data() + P.off_ut, P.units_ticket.data(), P.units_ticket.size() * 4);
-    std::memcpy(host.data() + P.off_ul, P.units_level.data(), P.units_level.size() * 4);
-    auto put = [&](size_t o, const std::vector<int32_t>& v) {
-        if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * 4);
-    };
-    put(P.off_up, P.units_prio);
-    if (!P.gidx.empty()) std::memcpy(host.data() + P.off_gidx, P.gidx.data(), P.gidx.size() * 8);
-    if (!P.dims.empty()) std::memcpy(host.data() + P.off_dims, P.dims.data(), P.dims.size() * 8);
-    void* d = nullptr;
-    if (hipMalloc(&d, off) != hipSuccess) return BB_ENOMEM;
-    if (hipMemcpy(d, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        return BB_EHIP;
+    if (!P.blob.alloc(off)) return BB_ENOMEM;
+    char* h = P.blob.p;
+    bbk::DevTask* dt = (bbk::DevTask*)(h + P.off_tasks);
+    for (size_t t = 0; t < nt; ++t) {
+        const bb::Task& s = P.g.tasks[t];
+        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
     }
-    P.dblob = d;
-    P.device = dev;
+    auto put32 = [&](size_t o, const std::vector<int32_t>& v) {
+        if (!v.empty()) std::memcpy(h + o, v.data(), v.size() * 4);
+    };
+    auto put64 = [&](size_t o, const std::vector<int64_t>& v) {
+        if (!v.empty()) std::memcpy(h + o, v.data(), v.size() * 8);
+    };
+    put32(P.off_ndeps, P.ndeps);
+    put32(P.off_succ_off, P.succ_off);
+    put32(P.off_succ_idx, P.succ_idx);
+    put32(P.off_units, units);
+    put64(P.off_gidx, P.gidx);
+    put64(P.off_dims, P.dims);
     return BB_OK;
 }
 
-// Enqueue one run of plan P on matrix A (arguments already validated).
-// Enqueue one run of plan P (arguments already validated).  d0: the only
-// matrix of a single-matrix plan; NULL when the descriptors of a batched plan
-// are already in the workspace.
-int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* stream) {
-    bb_plan* P = &Pr;
-    int rc = ensure_device(*P);
-    if (rc != BB_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
+// Enqueue the copy of the plan's graph into workspace ws (stream-ordered).
+int upload_graph(bb_plan& P, void* ws, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
+    if (dev < 32) P.used_devices.fetch_or(1u << dev);
+    if (hipMemcpyAsync((char*)ws + ws_blob_off(P), P.blob.p, P.blob.bytes, hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return BB_EHIP;
+    return BB_OK;
+}
 
+int device_attr(hipDeviceAttribute_t attr, int fallback) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, attr, dev) != hipSuccess || v <= 0)
+        return fallback;
+    return v;
+}
+
+int plan_events(bb_plan& P) {
+    std::call_once(P.ev_once, [&P] {
+        if (hipEventCreate(&P.ev0) != hipSuccess || hipEventCreate(&P.ev1) != hipSuccess)
+            P.ev_err = hipErrorInvalidValue;
+    });
+    return P.ev_err == hipSuccess ? BB_OK : BB_EHIP;
+}
+
+// Enqueue one run of plan P (arguments already validated, graph already
+// uploaded into ws on this stream).  d0: the only matrix of a single-matrix
+// plan; NULL when the descriptors of a batched plan are already in the
+// workspace.
+int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipStream_t s) {
     bbk::KArgs a{};
     if (d0) {
         a.single = *d0;
@@ -321,41 +374,56 @@ int launch_plan(bb_plan& Pr, const bbk::MatDesc* d0, void* vt, void* ws, void* s
         a.mats = (const bbk::MatDesc*)((char*)ws + ws_mats_off());
     }
     a.vt = (double*)vt;
-    a.slot_stride = bbk::record_doubles(P->nb);
-    char* blob = (char*)P->dblob;
-    a.tasks = (const bbk::DevTask*)(blob + P->off_tasks);
-    a.nunits = (int32_t)(P->units_ticket.size() / 2);
-    a.succ_off = (const int32_t*)(blob + P->off_succ_off);
-    a.succ_idx = (const int32_t*)(blob + P->off_succ_idx);
+    a.slot_stride = bbk::record_doubles(P.nb);
+    char* blob = (char*)ws + ws_blob_off(P);
+    a.tasks = (const bbk::DevTask*)(blob + P.off_tasks);
+    a.nunits = (int32_t)(P.units_ticket.size() / 2);
+    a.units = (const int2*)(blob + P.off_units);
+    a.succ_off = (const int32_t*)(blob + P.off_succ_off);
+    a.succ_idx = (const int32_t*)(blob + P.off_succ_idx);
     a.ctrl = (int32_t*)ws;
-    a.deps = (int32_t*)((char*)ws + ws_deps_off(*P));
-    a.watchdog_ticks = (int64_t)(P->opts.watchdog_s * P->wallclock_khz * 1000.0);
-    a.trace = (P->opts.flags & BB_FLAG_TRACE) ? (int64_t*)((char*)ws + ws_trace_off(*P)) : nullptr;
+    a.deps = (int32_t*)((char*)ws + ws_deps_off(P));
+    const double khz = (double)device_attr(hipDeviceAttributeWallClockRate, 100000);
+    a.watchdog_ticks = (int64_t)(P.opts.watchdog_s * khz * 1000.0);
+    a.trace = (P.opts.flags & BB_FLAG_TRACE) ? (int64_t*)((char*)ws + ws_trace_off(P)) : nullptr;
 
-    const bool timed = (P->opts.flags & BB_FLAG_TIMING) != 0;
-    if (timed && !P->ev0) {
-        if (hipEventCreate(&P->ev0) != hipSuccess || hipEventCreate(&P->ev1) != hipSuccess) return BB_EHIP;
-    }
-    const bool persistent = P->opts.sched == BB_SCHED_PERSISTENT;
-    a.units = (const int2*)(blob + (persistent ? P->off_up : P->off_ul));
-    if (bbk::launch_init(a, (const int32_t*)(blob + P->off_ndeps), (int32_t)P->g.tasks.size(), s) != hipSuccess)
+    const bool timed = (P.opts.flags & BB_FLAG_TIMING) != 0;
+    if (timed && plan_events(P) != BB_OK) return BB_EHIP;
+    const bool persistent = P.opts.sched == BB_SCHED_PERSISTENT;
+    if (bbk::launch_init(a, (const int32_t*)(blob + P.off_ndeps), (int32_t)P.g.tasks.size(), s) != hipSuccess)
         return BB_EHIP;
-    if (timed && hipEventRecord(P->ev0, s) != hipSuccess) return BB_EHIP;
+    if (timed && hipEventRecord(P.ev0, s) != hipSuccess) return BB_EHIP;
     if (a.nunits > 0) {
         if (persistent) {
-            int wg = std::min(P->opts.workgroups, P->cu_count > 0 ? P->cu_count : P->opts.workgroups);
+            const int cus = device_attr(hipDeviceAttributeMultiprocessorCount, P.opts.workgroups);
+            int wg = std::min(P.opts.workgroups, cus);
             wg = std::max(1, std::min(wg, a.nunits));
-            if (bbk::launch_persistent(P->nb, P->prec, a, wg, s) != hipSuccess) return BB_EHIP;
+            if (bbk::launch_persistent(P.nb, P.prec, a, wg, s) != hipSuccess) return BB_EHIP;
         } else {
-            for (size_t l = 0; l + 1 < P->level_off.size(); ++l) {
-                int32_t b = P->level_off[l], e = P->level_off[l + 1];
-                if (bbk::launch_level(P->nb, P->prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
+            for (size_t l = 0; l + 1 < P.level_off.size(); ++l) {
+                int32_t b = P.level_off[l], e = P.level_off[l + 1];
+                if (bbk::launch_level(P.nb, P.prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
             }
         }
     }
-    if (timed && hipEventRecord(P->ev1, s) != hipSuccess) return BB_EHIP;
-    P->timed = timed;
+    if (timed && hipEventRecord(P.ev1, s) != hipSuccess) return BB_EHIP;
+    P.timed = timed;
     return BB_OK;
+}
+
+int launch_plan(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = upload_graph(P, ws, s);
+    if (rc != BB_OK) return rc;
+    return launch_kernels(P, d0, vt, ws, s);
+}
+
+// Finish a plan whose graph is built: schedule, then the host copy of what
+// the device reads.
+int finish_plan(bb_plan& P) {
+    int rc = build_schedule(P);
+    if (rc != BB_OK) return rc;
+    return build_blob(P);
 }
 
 // The plan applying side (0: Q, 1: P), transposed or not, to ncols columns.
@@ -380,7 +448,7 @@ int get_apply(bb_plan* P, int side, int transpose, int64_t ncols, bb_plan** out)
     Q->opts = P->opts;
     try {
         bb::build_apply_graph(P->g, side, transpose, (int)jc, Q->g);
-        int rc = build_schedule(*Q);
+        int rc = finish_plan(*Q);
         if (rc != BB_OK) {
             delete Q;
             return rc;
@@ -415,14 +483,81 @@ int default_workgroups() {
     return 256;
 }
 
-std::mutex g_cache_mu;
-std::map<std::vector<double>, bb_plan*> g_cache;
+// The one-shot entry points keep a bounded number of recently used plans
+// (least recently used out first).  A call holds its plan through a shared
+// pointer, so a plan evicted (or dropped by bb_cache_clear) while another
+// thread executes it is destroyed only after that call returns.  The caches
+// are never destroyed themselves: plans left in them at exit are not torn
+// down after the HIP runtime.
+template <class Key, class T>
+struct PlanCache {
+    std::mutex mu;
+    size_t cap;
+    std::list<std::pair<Key, std::shared_ptr<T>>> items;   // most recently used first
+    explicit PlanCache(size_t c) : cap(c) {}
+    std::shared_ptr<T> find(const Key& k) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto it = items.begin(); it != items.end(); ++it)
+            if (it->first == k) {
+                items.splice(items.begin(), items, it);
+                return items.front().second;
+            }
+        return nullptr;
+    }
+    // Returns the cached plan for k: v, or one another thread inserted first.
+    std::shared_ptr<T> insert(const Key& k, std::shared_ptr<T> v) {
+        std::vector<std::shared_ptr<T>> dropped;   // destroyed outside the lock
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : items)
+            if (kv.first == k) return kv.second;
+        items.emplace_front(k, v);
+        while (items.size() > cap) {
+            dropped.push_back(items.back().second);
+            items.pop_back();
+        }
+        return v;
+    }
+    void clear() {
+        std::list<std::pair<Key, std::shared_ptr<T>>> old;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            old.swap(items);
+        }
+    }
+};
+
+constexpr size_t kPlanCacheSize = 16, kBatchCacheSize = 4;
+
+PlanCache<std::vector<double>, bb_plan>& plan_cache() {
+    static auto* c = new PlanCache<std::vector<double>, bb_plan>(kPlanCacheSize);
+    return *c;
+}
+
+PlanCache<std::vector<int64_t>, bb_batch>& batch_cache() {
+    static auto* c = new PlanCache<std::vector<int64_t>, bb_batch>(kBatchCacheSize);
+    return *c;
+}
 
 std::vector<double> cache_key(int64_t m, int64_t n, int nb, int tree, int variant, int prec,
                               const bb_opts& o) {
     return {(double)m, (double)n, (double)nb, (double)tree, (double)variant, (double)prec,
             (double)o.workgroups, o.gamma, (double)o.auto_a, (double)o.sched, o.watchdog_s,
             (double)o.flags};
+}
+
+// Wait until no copy enqueued from a plan's host memory can still be in
+// flight: every device the plan uploaded on is synchronized.
+void quiesce(bb_plan& P) {
+    const uint32_t mask = P.used_devices.load();
+    if (!mask) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    for (int d = 0; d < 32; ++d)
+        if (mask & (1u << d)) {
+            if (d != cur && hipSetDevice(d) != hipSuccess) continue;
+            (void)hipDeviceSynchronize();
+        }
+    (void)hipSetDevice(cur);
 }
 
 }  // namespace
@@ -484,7 +619,7 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
                 return BB_EDAG;
             }
         }
-        int rc = build_schedule(*P);
+        int rc = finish_plan(*P);
         if (rc != BB_OK) {
             delete P;
             return rc;
@@ -502,13 +637,17 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
 
 void bb_plan_destroy(bb_plan* P) {
     if (!P) return;
+    quiesce(*P);
     for (auto& kv : P->apply) bb_plan_destroy(kv.second);
     delete P->adj;
-    if (P->adj_dev) (void)hipFree(P->adj_dev);
-    if (P->dblob) (void)hipFree(P->dblob);
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
     delete P;
+}
+
+void bb_cache_clear(void) {
+    plan_cache().clear();
+    batch_cache().clear();
 }
 
 int bb_plan_workspace(const bb_plan* P, size_t* vt_bytes, size_t* ws_bytes) {
@@ -624,18 +763,42 @@ int bb_apply_p(bb_plan* P, int transpose, const void* vt, size_t vt_bytes, void*
 namespace {
 
 // Workspace of the adjoint: G, G^T (n x n), the Omega and Psi bar grids
-// (npad x npad), scratch (npad x 3nb), then the apply plans' state.
+// (npad x npad), scratch (npad x 3nb), the inverted diagonal blocks, the copy
+// of the operation list, then the state of the two applications (P, then Q),
+// each in its own region so that both error words survive the call.
 struct AdjLayout {
-    size_t g, gt, om, ps, tmp, inv, apply, total;
+    size_t g, gt, om, ps, tmp, inv, ops, apply_p, apply_q, total;
 };
+
+// Builds (once) the adjoint's operation list and its host copy.
+int adjoint_ops(bb_plan* P, const bbk::AdjointOps** out) {
+    std::lock_guard<std::mutex> lk(P->adj_mu);
+    if (!P->adj) {
+        try {
+            std::unique_ptr<bbk::AdjointOps> ops(new bbk::AdjointOps());
+            bbk::build_adjoint_ops(P->m, P->n, P->nb, *ops);
+            const size_t bytes = ops->ops.size() * sizeof(bbk::AOp);
+            if (!P->adj_blob.alloc(bytes)) return BB_ENOMEM;
+            if (bytes) std::memcpy(P->adj_blob.p, ops->ops.data(), bytes);
+            P->adj = ops.release();
+        } catch (const std::bad_alloc&) {
+            return BB_ENOMEM;
+        }
+    }
+    *out = P->adj;
+    return BB_OK;
+}
 
 int adjoint_layout(bb_plan* P, AdjLayout& L) {
     const int64_t n = P->n, nb = P->nb;
     const int64_t npad = (n + nb - 1) / nb * nb;
     bb_plan *Qp = nullptr, *Pp = nullptr;
+    const bbk::AdjointOps* ops = nullptr;
     int rc = get_apply(P, 1, 0, n, &Pp);
     if (rc != BB_OK) return rc;
     rc = get_apply(P, 0, 0, n, &Qp);
+    if (rc != BB_OK) return rc;
+    rc = adjoint_ops(P, &ops);
     if (rc != BB_OK) return rc;
     size_t off = 0;
     L.g = off; off = round_up(off + sizeof(double) * n * n, 256);
@@ -644,7 +807,9 @@ int adjoint_layout(bb_plan* P, AdjLayout& L) {
     L.ps = off; off = round_up(off + sizeof(double) * npad * npad, 256);
     L.tmp = off; off = round_up(off + sizeof(double) * npad * 3 * nb, 256);
     L.inv = off; off = round_up(off + sizeof(double) * npad * 2 * nb, 256);
-    L.apply = off; off += std::max(ws_bytes_of(*Qp), ws_bytes_of(*Pp));
+    L.ops = off; off = round_up(off + P->adj_blob.bytes, 256);
+    L.apply_p = off; off = round_up(off + ws_bytes_of(*Pp), 256);
+    L.apply_q = off; off = round_up(off + ws_bytes_of(*Qp), 256);
     L.total = off;
     return BB_OK;
 }
@@ -678,27 +843,16 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     int rc = adjoint_layout(P, L);
     if (rc != BB_OK) return rc;
     if (ws_bytes < L.total) return BB_EWORKSPACE;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
-    try {
-        if (!P->adj) {
-            P->adj = new bbk::AdjointOps();
-            bbk::build_adjoint_ops(P->m, P->n, P->nb, *P->adj);
-        }
-    } catch (const std::bad_alloc&) {
-        return BB_ENOMEM;
-    }
-    const bbk::AdjointOps& ops = *P->adj;
-    if (!P->adj_dev || P->adj_device != dev) {
-        if (P->adj_dev) (void)hipFree(P->adj_dev);
-        P->adj_dev = nullptr;
-        const size_t bytes = ops.ops.size() * sizeof(bbk::AOp);
-        if (hipMalloc(&P->adj_dev, std::max<size_t>(bytes, 256)) != hipSuccess) return BB_ENOMEM;
-        if (hipMemcpy(P->adj_dev, ops.ops.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return BB_EHIP;
-        P->adj_device = dev;
-    }
+    const bbk::AdjointOps* opsp = nullptr;
+    if ((rc = adjoint_ops(P, &opsp)) != BB_OK) return rc;
+    const bbk::AdjointOps& ops = *opsp;
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BB_EHIP;
+    if (dev < 32) P->used_devices.fetch_or(1u << dev);
+    if (hipMemcpyAsync(w + L.ops, P->adj_blob.p, P->adj_blob.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return BB_EHIP;
     const int64_t n = P->n, npad = ops.npad;
     bbk::AArgs a{};
     a.buf[bbk::AB_B] = {(double*)B, ldb};
@@ -710,7 +864,7 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     a.buf[bbk::AB_TMP] = {(double*)(w + L.tmp), npad};
     a.buf[bbk::AB_ABAR] = {(double*)Abar, ldabar};
     a.buf[bbk::AB_INV] = {(double*)(w + L.inv), npad};
-    const bbk::AOp* dops = (const bbk::AOp*)P->adj_dev;
+    const bbk::AOp* dops = (const bbk::AOp*)(w + L.ops);
     auto run_stages = [&](int32_t s0, int32_t s1) -> int {
         for (int32_t st = s0; st < s1; ++st) {
             const int32_t o0 = ops.stage_off[st], o1 = ops.stage_off[st + 1];
@@ -727,11 +881,31 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     if ((rc = get_apply(P, 1, 0, n, &Pp)) != BB_OK) return rc;
     if ((rc = get_apply(P, 0, 0, n, &Qp)) != BB_OK) return rc;
     const bbk::MatDesc dP{(double*)(w + L.gt), n, n, n};
-    if ((rc = launch_plan(*Pp, &dP, const_cast<void*>(vt), w + L.apply, stream)) != BB_OK) return rc;
+    if ((rc = launch_plan(*Pp, &dP, const_cast<void*>(vt), w + L.apply_p, stream)) != BB_OK) return rc;
     rc = run_stages(ops.finish_stage, nst);
     if (rc != BB_OK) return rc;
     const bbk::MatDesc dQ{(double*)Abar, ldabar, P->m, n};
-    return launch_plan(*Qp, &dQ, const_cast<void*>(vt), w + L.apply, stream);
+    return launch_plan(*Qp, &dQ, const_cast<void*>(vt), w + L.apply_q, stream);
+}
+
+int bb_adjoint_poll_error(bb_plan* P, const void* ws, void* stream, int* device_status) {
+    if (!P) return -1;
+    if (!ws) return -2;
+    if (!device_status) return -4;
+    AdjLayout L;
+    int rc = adjoint_layout(P, L);
+    if (rc != BB_OK) return rc;
+    *device_status = 0;
+    for (size_t off : {L.apply_p, L.apply_q}) {
+        int st = 0;
+        rc = bb_poll_error((const char*)ws + off, stream, &st);
+        if (rc != BB_OK) return rc;
+        if (st != 0) {
+            *device_status = st;
+            break;
+        }
+    }
+    return BB_OK;
 }
 
 int bb_plan_trace(bb_plan* P, size_t* offset, int64_t* nunits, double* tick_hz, int32_t* units) {
@@ -739,17 +913,7 @@ int bb_plan_trace(bb_plan* P, size_t* offset, int64_t* nunits, double* tick_hz, 
     if (!(P->opts.flags & BB_FLAG_TRACE)) return BB_ENOTSUP;
     if (offset) *offset = ws_trace_off(*P);
     if (nunits) *nunits = (int64_t)(P->units_ticket.size() / 2);
-    if (tick_hz) {
-        if (P->wallclock_khz <= 0.0) {
-            int dev = 0, khz = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
-                khz = 100000;
-            *tick_hz = 1000.0 * khz;
-        } else {
-            *tick_hz = 1000.0 * P->wallclock_khz;
-        }
-    }
+    if (tick_hz) *tick_hz = 1000.0 * (double)device_attr(hipDeviceAttributeWallClockRate, 100000);
     if (units) std::copy(P->units_prio.begin(), P->units_prio.end(), units);
     return BB_OK;
 }
@@ -765,13 +929,34 @@ int bb_plan_last_kernel_ms(bb_plan* P, double* ms) {
     return BB_OK;
 }
 
+namespace {
+
+// The cached plan of the one-shot entry points for these arguments, built
+// on first use.  Returns BB_OK or bb_plan_create's code.
+int cached_plan(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts& o,
+                std::shared_ptr<bb_plan>& out) {
+    std::vector<double> key = cache_key(m, n, nb, tree, variant, prec, o);
+    out = plan_cache().find(key);
+    if (out) return BB_OK;
+    bb_plan* P = nullptr;
+    int rc = bb_plan_create(&P, m, n, nb, tree, variant, prec, &o);
+    if (rc != BB_OK) return rc;
+    try {
+        out = plan_cache().insert(key, std::shared_ptr<bb_plan>(P, bb_plan_destroy));
+    } catch (const std::bad_alloc&) {
+        return BB_ENOMEM;
+    }
+    return BB_OK;
+}
+
+}  // namespace
+
 int bb_query(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
              size_t* vt_bytes, size_t* ws_bytes) {
-    bb_plan* P = nullptr;
-    int rc = bb_plan_create(&P, m, n, nb, tree, variant, prec, opts);
+    std::shared_ptr<bb_plan> P;
+    int rc = cached_plan(m, n, nb, tree, variant, prec, resolved_opts(opts), P);
     if (rc != BB_OK) return rc;
-    bb_plan_workspace(P, vt_bytes, ws_bytes);
-    bb_plan_destroy(P);
+    bb_plan_workspace(P.get(), vt_bytes, ws_bytes);
     return BB_OK;
 }
 
@@ -782,28 +967,17 @@ int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, in
     if (lda < std::max<int64_t>(1, m)) return -4;
     if (!vt) return -9;
     if (!ws) return -11;
-    bb_opts o = resolved_opts(opts);
-    std::vector<double> key = cache_key(m, n, nb, tree, variant, prec, o);
-    bb_plan* P = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
-            P = it->second;
-        } else {
-            int rc = bb_plan_create(&P, m, n, nb, tree, variant, prec, &o);
-            if (rc != BB_OK) {
-                // map plan-creation argument numbers onto this entry point's
-                if (rc < 0) {
-                    static const int remap[9] = {0, 0, -2, -3, -5, -6, -7, -8, -13};
-                    return rc >= -8 ? remap[-rc] : rc;
-                }
-                return rc;
-            }
-            g_cache[key] = P;
+    std::shared_ptr<bb_plan> P;
+    int rc = cached_plan(m, n, nb, tree, variant, prec, resolved_opts(opts), P);
+    if (rc != BB_OK) {
+        // map plan-creation argument numbers onto this entry point's
+        if (rc < 0) {
+            static const int remap[9] = {0, 0, -2, -3, -5, -6, -7, -8, -13};
+            return rc >= -8 ? remap[-rc] : rc;
         }
+        return rc;
     }
-    int rc = bb_execute(P, A, lda, vt, vt_bytes, ws, ws_bytes, stream);
+    rc = bb_execute(P.get(), A, lda, vt, vt_bytes, ws, ws_bytes, stream);
     if (rc == -3) return -4;
     if (rc == -4) return -9;
     if (rc == -6) return -11;
@@ -970,7 +1144,7 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
                 bb::append_graph(P->g, gi, (int32_t)li);
                 if (P->g.tasks.size() > (size_t)INT32_MAX / 2) { delete B; return BB_ENOTSUP; }
             }
-            int rc = build_schedule(*P);
+            int rc = finish_plan(*P);
             if (rc != BB_OK) { delete B; return rc; }
         }
         size_t vt_off = 0, ws_off = 0;
@@ -1028,21 +1202,29 @@ int bb_batch_execute(bb_batch* B, double* const* A, const int64_t* lda, void* vt
     if (ws_bytes < B->ws_bytes) return BB_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     const bool timed = (B->opts.flags & BB_FLAG_TIMING) != 0;
-    if (timed && !B->ev0) {
-        if (hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess) return BB_EHIP;
+    if (timed) {
+        std::call_once(B->ev_once, [B] {
+            if (hipEventCreate(&B->ev0) != hipSuccess || hipEventCreate(&B->ev1) != hipSuccess)
+                B->ev_err = hipErrorInvalidValue;
+        });
+        if (B->ev_err != hipSuccess) return BB_EHIP;
     }
-    if (timed && hipEventRecord(B->ev0, s) != hipSuccess) return BB_EHIP;
+    // Every group's graph and descriptors first, so that the timed region
+    // holds the reduction kernels only.
     for (bb_batch::Group& grp : B->groups) {
         bb_plan& P = *grp.plan;
-        int rc = ensure_device(P);
-        if (rc != BB_OK) return rc;
         char* w = (char*)ws + grp.ws_off;
-        char* blob = (char*)P.dblob;
+        int rc = upload_graph(P, w, s);
+        if (rc != BB_OK) return rc;
+        char* blob = w + ws_blob_off(P);
         if (bbk::launch_batch_desc((bbk::MatDesc*)(w + ws_mats_off()), P.nmats,
                                    (const int64_t*)(blob + P.off_gidx), (const int64_t*)(blob + P.off_dims),
                                    A, lda, s) != hipSuccess)
             return BB_EHIP;
-        rc = launch_plan(P, nullptr, (char*)vt + grp.vt_off, w, stream);
+    }
+    if (timed && hipEventRecord(B->ev0, s) != hipSuccess) return BB_EHIP;
+    for (bb_batch::Group& grp : B->groups) {
+        int rc = launch_kernels(*grp.plan, nullptr, (char*)vt + grp.vt_off, (char*)ws + grp.ws_off, s);
         if (rc != BB_OK) return rc;
     }
     if (timed && hipEventRecord(B->ev1, s) != hipSuccess) return BB_EHIP;
@@ -1088,11 +1270,6 @@ int bb_query_batched(int64_t count, const int64_t* m, const int64_t* n, const in
     return BB_OK;
 }
 
-namespace {
-std::mutex g_bcache_mu;
-std::map<std::vector<int64_t>, bb_batch*> g_bcache;
-}  // namespace
-
 int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, const int64_t* m,
                         const int64_t* n, const int* nb, const int* tree, const int* variant, int prec,
                         void* vt, size_t vt_bytes, void* ws, size_t ws_bytes, const bb_opts* opts,
@@ -1124,26 +1301,25 @@ int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, con
     } catch (const std::bad_alloc&) {
         return BB_ENOMEM;
     }
-    bb_batch* B = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_bcache_mu);
-        auto it = g_bcache.find(key);
-        if (it != g_bcache.end()) {
-            B = it->second;
-        } else {
-            int rc = bb_batch_create(&B, count, m, n, nb, tree, variant, prec, &o);
-            if (rc != BB_OK) {
-                if (rc < 0) {
-                    // bb_batch_create numbering -> this entry point's
-                    static const int remap[10] = {0, 0, -3, -4, -5, -6, -7, -8, -9, -14};
-                    return rc >= -9 ? remap[-rc] : rc;
-                }
-                return rc;
+    std::shared_ptr<bb_batch> B = batch_cache().find(key);
+    if (!B) {
+        bb_batch* b = nullptr;
+        int rc = bb_batch_create(&b, count, m, n, nb, tree, variant, prec, &o);
+        if (rc != BB_OK) {
+            if (rc < 0) {
+                // bb_batch_create numbering -> this entry point's
+                static const int remap[10] = {0, 0, -3, -4, -5, -6, -7, -8, -9, -14};
+                return rc >= -9 ? remap[-rc] : rc;
             }
-            g_bcache[key] = B;
+            return rc;
+        }
+        try {
+            B = batch_cache().insert(key, std::shared_ptr<bb_batch>(b, bb_batch_destroy));
+        } catch (const std::bad_alloc&) {
+            return BB_ENOMEM;
         }
     }
-    int rc = bb_batch_execute(B, A, lda, vt, vt_bytes, ws, ws_bytes, stream);
+    int rc = bb_batch_execute(B.get(), A, lda, vt, vt_bytes, ws, ws_bytes, stream);
     switch (rc) {
     case -2: return -1;
     case -3: return -2;

@@ -62,8 +62,24 @@ def test_workspace_sizes():
     st = p.stats()
     vt, ws = p.workspace()
     assert vt == st["nslots"] * (128 * 128 + 16 * 128) * 8
-    assert ws >= 4 * st["ntasks"]
+    # counters and the uploaded graph copy (32-byte task records, initial
+    # counts, successor lists, 8 bytes per unit)
+    assert ws >= (4 + 32 + 4 + 8) * st["ntasks"]
     assert st["p"] == 8 and st["q"] == 6
+
+
+def test_one_shot_cache_is_bounded_and_clearable():
+    """bb_query fills the one-shot plan cache; more distinct shapes than its
+    capacity, then bb_cache_clear, leave later queries correct."""
+    sizes = {}
+    for k in range(40):
+        m, n = 200 + 8 * k, 100 + 4 * k
+        sizes[(m, n)] = bb.query(m, n, 64, "greedy", "bidiag")
+    bb.cache_clear()
+    for (m, n), s in list(sizes.items())[::7]:
+        assert bb.query(m, n, 64, "greedy", "bidiag") == s
+        p = bb.Plan(m, n, 64, "greedy", "bidiag")
+        assert p.workspace() == s
 
 
 @pytest.mark.parametrize("p", range(2, 22))
@@ -226,9 +242,13 @@ def test_apply_workspace_and_argument_errors():
     for side, ncols in ((0, 200), (1, 200), (0, 7), (1, 129)):
         npan = int(np.sum(panels[:, 1] == side))
         jc = -(-ncols // 64)
-        expect = 512 + -(-(4 * npan * jc) // 256) * 256
+        # scheduler words and one counter per task, then the uploaded copy of
+        # the graph: at least one 32-byte task record and one counter per task
+        state = 512 + -(-(4 * npan * jc) // 256) * 256
         for tr in (0, 1):
-            assert p.apply_workspace(side, tr, ncols) == expect
+            ws = p.apply_workspace(side, tr, ncols)
+            assert ws % 256 == 0 and ws >= state + 36 * npan * jc, (ws, state)
+            assert p.apply_workspace(side, tr, ncols) == ws
     assert p.apply_workspace(0, 0, 0) == 0
     v8 = ctypes.c_void_p(8)
     ws = p.apply_workspace(0, 0, 5)
