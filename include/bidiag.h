@@ -169,6 +169,24 @@ int bb_execute(bb_plan* plan, void* A, int64_t lda, void* vt, size_t vt_bytes, v
                size_t ws_bytes, void* stream);
 
 /*
+ * bb_execute_noalloc -- bb_execute without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The scheduler state and
+ * the task graph go to a workspace the library holds in a file-scope device
+ * array of BB_NOALLOC_WS_MAX bytes, one per device, kept until the process
+ * ends; the call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and records no timing events.  A plan whose
+ * bb_plan_workspace ws_bytes exceeds BB_NOALLOC_WS_MAX is rejected with
+ * BB_EWORKSPACE.  Every call on a device shares that device's array, so
+ * calls whose executions overlap on one device (other streams, other
+ * threads) race; calls in one stream order do not.  Arguments as
+ * bb_execute: plan (1), A (2), lda (3), vt (4), vt_bytes (5), stream (6).
+ * Scheduler errors: bb_poll_error with ws = NULL.
+ */
+#define BB_NOALLOC_WS_MAX (32u << 20)
+int bb_execute_noalloc(bb_plan* plan, void* A, int64_t lda, void* vt, size_t vt_bytes, void* stream);
+
+/*
  * bidiag_band -- one-shot form of bb_plan_create + bb_execute with a plan
  * cached inside the library by (m, n, nb, tree, variant, prec, opts).  The
  * cache holds at most 16 plans (least recently used out first; bb_query
@@ -331,7 +349,8 @@ int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, con
 /*
  * bb_poll_error -- synchronize `stream` and read the scheduler's error word
  * from ws: *device_status = 0 if the last execution completed, else a BB_E*
- * code.  Returns BB_OK or BB_EHIP.
+ * code.  ws = NULL reads the word of the last bb_execute_noalloc on the
+ * current device.  Returns BB_OK or BB_EHIP.
  */
 int bb_poll_error(const void* ws, void* stream, int* device_status);
 

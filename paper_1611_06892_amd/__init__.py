@@ -58,7 +58,8 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_tuned_config", "bb_batch_create", "bb_batch_destroy", "bb_batch_workspace",
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
-           "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear"]
+           "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear",
+           "bb_execute_noalloc"]
 
 
 def lib():
@@ -139,6 +140,8 @@ def lib():
     L.bb_adjoint_workspace.restype = i32
     L.bb_adjoint_poll_error.argtypes = [P, vp, vp, ip]
     L.bb_adjoint_poll_error.restype = i32
+    L.bb_execute_noalloc.argtypes = [P, vp, i64, vp, ctypes.c_size_t, vp]
+    L.bb_execute_noalloc.restype = i32
     L.bb_cache_clear.argtypes = []
     L.bb_cache_clear.restype = None
     L.bb_plan_trace.argtypes = [P, szp, lp, ctypes.POINTER(ctypes.c_double), vp]
@@ -273,6 +276,14 @@ class Plan:
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                 _stream_handle(stream)), "bb_execute")
 
+    def execute_noalloc(self, Acm, lda, vt, stream=None):
+        """bb_execute with the library's own per-device workspace (no device
+        allocation; overlapping calls on one device race)."""
+        _check(lib().bb_execute_noalloc(self._h, ctypes.c_void_p(Acm.data_ptr()), int(lda),
+                                        ctypes.c_void_p(vt.data_ptr()),
+                                        vt.numel() * vt.element_size(), _stream_handle(stream)),
+               "bb_execute_noalloc")
+
     def apply_workspace(self, side, transpose, ncols) -> int:
         ws = ctypes.c_size_t()
         _check(lib().bb_apply_workspace(self._h, int(side), int(transpose), int(ncols),
@@ -360,9 +371,11 @@ class Plan:
 
 
 def poll_error(ws, stream=None) -> int:
+    """Scheduler status of the last execution on workspace ws (synchronizes the
+    stream); ws=None: of the last bb_execute_noalloc on the current device."""
     st = ctypes.c_int()
-    _check(lib().bb_poll_error(ctypes.c_void_p(ws.data_ptr()), _stream_handle(stream),
-                               ctypes.byref(st)), "bb_poll_error")
+    wp = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
+    _check(lib().bb_poll_error(wp, _stream_handle(stream), ctypes.byref(st)), "bb_poll_error")
     return st.value
 
 

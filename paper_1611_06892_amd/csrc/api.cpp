@@ -365,7 +365,8 @@ int plan_events(bb_plan& P) {
 // uploaded into ws on this stream).  d0: the only matrix of a single-matrix
 // plan; NULL when the descriptors of a batched plan are already in the
 // workspace.
-int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipStream_t s) {
+int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipStream_t s,
+                   bool allow_timing = true) {
     bbk::KArgs a{};
     if (d0) {
         a.single = *d0;
@@ -387,7 +388,7 @@ int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipSt
     a.watchdog_ticks = (int64_t)(P.opts.watchdog_s * khz * 1000.0);
     a.trace = (P.opts.flags & BB_FLAG_TRACE) ? (int64_t*)((char*)ws + ws_trace_off(P)) : nullptr;
 
-    const bool timed = (P.opts.flags & BB_FLAG_TIMING) != 0;
+    const bool timed = allow_timing && (P.opts.flags & BB_FLAG_TIMING) != 0;
     if (timed && plan_events(P) != BB_OK) return BB_EHIP;
     const bool persistent = P.opts.sched == BB_SCHED_PERSISTENT;
     if (bbk::launch_init(a, (const int32_t*)(blob + P.off_ndeps), (int32_t)P.g.tasks.size(), s) != hipSuccess)
@@ -407,7 +408,7 @@ int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipSt
         }
     }
     if (timed && hipEventRecord(P.ev1, s) != hipSuccess) return BB_EHIP;
-    P.timed = timed;
+    if (allow_timing) P.timed = timed;
     return BB_OK;
 }
 
@@ -712,6 +713,24 @@ int bb_execute(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void
     return launch_plan(*P, &d0, vt, ws, stream);
 }
 
+int bb_execute_noalloc(bb_plan* P, void* A, int64_t lda, void* vt, size_t vt_bytes, void* stream) {
+    if (!P) return -1;
+    if (!A) return -2;
+    if (lda < std::max<int64_t>(1, P->m)) return -3;
+    if (!vt) return -4;
+    if (vt_bytes < vt_bytes_of(*P)) return BB_EWORKSPACE;
+    if (ws_bytes_of(*P) > (size_t)BB_NOALLOC_WS_MAX) return BB_EWORKSPACE;
+    void* ws = nullptr;
+    size_t cap = 0;
+    if (bbk::noalloc_scratch(&ws, &cap) != hipSuccess) return BB_EHIP;
+    if (ws_bytes_of(*P) > cap) return BB_EWORKSPACE;
+    const bbk::MatDesc d0{(double*)A, lda, P->m, P->n};
+    hipStream_t s = (hipStream_t)stream;
+    int rc = upload_graph(*P, ws, s);
+    if (rc != BB_OK) return rc;
+    return launch_kernels(*P, &d0, vt, ws, s, /*allow_timing=*/false);
+}
+
 int bb_apply_workspace(bb_plan* P, int side, int transpose, int64_t ncols, size_t* ws_bytes) {
     if (!P) return -1;
     if (side != 0 && side != 1) return -2;
@@ -985,8 +1004,14 @@ int bidiag_band(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, in
 }
 
 int bb_poll_error(const void* ws, void* stream, int* device_status) {
-    if (!ws) return -1;
     if (!device_status) return -3;
+    if (!ws) {
+        // the workspace of bb_execute_noalloc on the current device
+        void* p = nullptr;
+        size_t cap = 0;
+        if (bbk::noalloc_scratch(&p, &cap) != hipSuccess) return BB_EHIP;
+        ws = p;
+    }
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return BB_EHIP;
     int32_t e = 0;
     if (hipMemcpy(&e, (const char*)ws + sizeof(int32_t) * bbk::CTRL_ERROR, sizeof(int32_t),

@@ -23,8 +23,10 @@
 // register-resident 16-column slices of the trailing tile(s), one slice per
 // wave.  Two waves per SIMD let one wave's MFMA chain run while the other
 // waits on a dependency.
+#include <mutex>
 #include <type_traits>
 
+#include "../../include/bidiag.h"
 #include "kernels.hpp"
 
 namespace bbk {
@@ -1077,6 +1079,34 @@ hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, 
 }
 
 bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128; }
+
+// Workspace of bb_execute_noalloc: a file-scope device array, one copy per
+// device for the life of the process.  Host code never passes the array's
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): the device address of each device's copy is looked up once, with
+// that device current, and used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[BB_NOALLOC_WS_MAX];
+
+hipError_t noalloc_scratch(void** ptr, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = BB_NOALLOC_WS_MAX;
+    return hipSuccess;
+}
 
 #define BB_DISPATCH(KERNEL, GRID, ...)                                                   \
     switch (nb * 4 + prec) {                                                             \

@@ -59,4 +59,8 @@ hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int
 hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s);
 bool nb_supported(int nb);
 
+// Workspace for callers that cannot allocate: the current device's copy of a
+// file-scope device array of *bytes bytes (looked up once per device).
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
+
 }  // namespace bbk
