@@ -54,7 +54,7 @@ extern "C" {
 
 /* ---- error codes ------------------------------------------------------- */
 #define BB_OK        0
-#define BB_ENOTSUP   1   /* valid but unsupported request (e.g. m < n, nb not in {32,64,128}) */
+#define BB_ENOTSUP   1   /* valid but unsupported request (e.g. m < n, nb not in {32,64,128,256}) */
 #define BB_EHIP      2   /* a HIP runtime call failed */
 #define BB_ETIMEOUT  3   /* the device scheduler's watchdog fired (no progress) */
 #define BB_EDAG      4   /* the task graph failed validation on the host */
@@ -117,8 +117,9 @@ typedef struct {
 /*
  * bb_plan_create -- build the task graph of one reduction (host work only: no
  * device memory and no device work; the host copy of the graph is
- * page-locked when a device is present).  Arguments: out plan (1), m (2), n (3) with m >= n >= 1, nb (4) in
- * {32, 64, 128}, tree (5) BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64*,
+ * page-locked when a device is present).  Arguments: out plan (1), m (2),
+ * n (3) with m >= n >= 1, nb (4) in {32, 64, 128, 256}, tree (5)
+ * BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64*,
  * opts (8, may be NULL for defaults).  The plan is independent of the data and
  * of lda; it can be executed any number of times.
  */
@@ -253,8 +254,8 @@ int bb_apply_workspace(bb_plan* plan, int side, int transpose, int64_t ncols, si
  * with vt_bytes (7): that reduction's records; Abar (8) m x n device output,
  * ldabar (9) >= m; ws (10) / ws_bytes (11) >= bb_adjoint_workspace; stream
  * (12).  FP64.  The gradient exists where every diagonal and super-diagonal
- * block of B is nonsingular (true almost surely); BB_QRONLY plans return
- * BB_ENOTSUP.
+ * block of B is nonsingular (true almost surely); BB_QRONLY plans and
+ * plans with nb = 256 return BB_ENOTSUP.
  */
 int bidiag_band_adjoint(bb_plan* plan, const void* B, int64_t ldb, const void* W, int64_t ldw,
                         const void* vt, size_t vt_bytes, void* Abar, int64_t ldabar, void* ws,

@@ -858,6 +858,7 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     if (ldabar < std::max<int64_t>(1, P->m)) return -9;
     if (!ws) return -10;
     if (P->variant == BB_QRONLY) return BB_ENOTSUP;
+    if (P->nb > 128) return BB_ENOTSUP;     // the sweep's block solves cover nb <= 128
     AdjLayout L;
     int rc = adjoint_layout(P, L);
     if (rc != BB_OK) return rc;
@@ -1119,7 +1120,7 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
         B->rec_off.assign(count, 0);
         B->nrec.assign(count, 0);
         const size_t wsg = 256;
-        for (int tile : {32, 64, 128}) {
+        for (int tile : {32, 64, 128, 256}) {
             std::vector<int64_t> idx;
             for (int64_t i = 0; i < count; ++i)
                 if (B->nb[i] == tile) idx.push_back(i);

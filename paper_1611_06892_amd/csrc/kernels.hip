@@ -42,7 +42,9 @@ template <int NB>
 struct Shape {
     static constexpr int MT = NB / 16;                 // 16 x 16 tiles per tile side
     static constexpr int LDL = NB + 1;                 // LDS stride of the leaf (odd: conflict-free)
-    static constexpr int PANEL = 16 * LDL + 2 * NB + 16 + 768;   // doubles used by a panel
+    // doubles used by a panel: leaf buffer(s) (two at nb = 256), then the
+    // reflector broadcast, taus, G, T_b and R1's diagonal entries
+    static constexpr int PANEL = (NB > 128 ? 32 : 16) * LDL + 2 * NB + 16 + 768;
     static constexpr int UPDATE = 2 * (16 * LDL + 256);           // ... and by an update
     static constexpr int LDS = PANEL > UPDATE ? PANEL : UPDATE;
 };
@@ -349,6 +351,104 @@ __device__ __forceinline__ void retire(const KArgs& a, Prev& p) {
 }
 
 // ---------------------------------------------------------------------------
+// Application of the first NBLK 16-column blocks of a panel record to a
+// 16-column slice per wave (the body of UNMQR/TSMQR/TTMQR, Table 1).  Wave
+// w's slice c2 (logical columns c0 .. c0 + 15 of C2, all NB rows, in the
+// MFMA result layout) is already in registers; block b+1 of the record is
+// fetched from memory while block b is applied, then staged in LDS for all
+// eight waves:
+//   W = C1(block-row b) + V_b^T C2     (UNMQR: no C1)
+//   W = T_b^T W
+//   C1(block-row b) -= W,   C2 -= V_b W
+// which is Q^T [C1; C2] for Q = Q_0 Q_1 ... (Section 3.2).  Zero 16 x 16
+// blocks of V are skipped: V is unit lower triangular after GEQRT and upper
+// triangular after TTQRT.  HQ applies Q itself (used to form Q C and P C
+// from the records): the blocks in reverse order, each with T_b instead of
+// T_b^T.  The previous unit of the workgroup is retired once the first
+// record block's loads are issued.
+// ---------------------------------------------------------------------------
+template <int NB, int NBLK, int KIND, bool CO, bool HQ>
+__device__ __forceinline__ void apply_blocks(const Rec& rec, const TileView& T1, int c0, bool active,
+                                             d4* c2, double* lds, const KArgs& a, Prev& prev) {
+    constexpr int MT = NB / 16;
+    constexpr int LDV = NB + 1;
+    constexpr int BUF = 16 * LDV + 256;       // V_b (NB x 16, stride LDV) then T_b^T (16 x 16)
+    constexpr int PRE = 16 * NB / NT + 1;     // staged doubles per thread and block
+    constexpr bool HASC1 = KIND != K_UNMQR;
+    const int tid = threadIdx.x, lane = tid & 63, j = lane & 15, g = lane >> 4;
+
+    // Block b of the record: V(:, 16b..16b+15) is contiguous (column-major),
+    // T_b^T follows the nb x nb matrix.  Thread t stages elements t + NT k of
+    // V_b and element t of T_b^T (t < 256).
+    auto fetch = [&](int b, double (&pre)[PRE]) {
+#pragma unroll
+        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + NT * k), 8 * (16 * b * NB));
+        pre[PRE - 1] = tid < 256 ? rec.ld(8 * tid, 8 * (NB * NB + 256 * b)) : 0.0;
+    };
+    auto stage = [&](int buffer, const double (&pre)[PRE]) {
+        double* buf = lds + buffer * BUF;
+#pragma unroll
+        for (int k = 0; k < PRE - 1; ++k) {
+            const int e = tid + NT * k;
+            buf[(e % NB) + (e / NB) * LDV] = pre[k];
+        }
+        if (tid < 256) buf[16 * LDV + tid] = pre[PRE - 1];
+    };
+    auto blk = [](int step) { return HQ ? NBLK - 1 - step : step; };
+
+    double pre[PRE];
+    fetch(blk(0), pre);
+    retire(a, prev);
+    stage(0, pre);
+    d4 C1n = {0.0, 0.0, 0.0, 0.0};
+    if (HASC1 && active) C1n = load16(T1, 16 * blk(0), c0);
+    lds_barrier();
+#pragma unroll
+    for (int st = 0; st < NBLK; ++st) {
+        const int b = blk(st);
+        const double* Vs = lds + (st & 1) * BUF;
+        const double* Ts = Vs + 16 * LDV;
+        if (st + 1 < NBLK) fetch(blk(st + 1), pre);
+        const d4 C1b = C1n;
+        if (HASC1 && active && st + 1 < NBLK) C1n = load16(T1, 16 * blk(st + 1), c0);
+        if (active) {
+            // Two accumulators halve the dependent-MFMA chain of W.
+            d4 Wp[2] = {C1b, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Wp[r & 1] = mfma(Vs[(16 * i + 4 * r + g) + j * LDV], c2[i][r], Wp[r & 1]);
+                // at nb = 256 the slice takes half the registers: keep the
+                // operand loads of later row tiles from being hoisted
+                if (MT > 8 && (i & 1)) SCHED_FENCE();
+            }
+            const d4 W = Wp[0] + Wp[1];
+            d4 W2 = {0.0, 0.0, 0.0, 0.0};
+            // Ts holds T_b^T column-major: T_b(k, i) at i + 16 k.
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                W2 = mfma(-(HQ ? Ts[(4 * r + g) + 16 * j] : Ts[j + 16 * (4 * r + g)]), W[r], W2);
+            // W2 holds -T_b^T W: negating the 4 T operands spares negating
+            // the V operands of the update below.
+            if (HASC1) store16<CO>(T1, 16 * b, c0, C1b + W2);
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                if (KIND == K_UNMQR && i < b) continue;
+                if (KIND == K_TTMQR && i > b) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c2[i] = mfma(Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
+                if (MT > 8 && (i & 1)) SCHED_FENCE();
+            }
+        }
+        if (st + 1 < NBLK) stage((st + 1) & 1, pre);
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Panel kernels: GEQRT, TSQRT, TTQRT (Table 1), blocked by 16 columns.
 //
 // GEQRT factors the tile X = T1 (R overwrites its upper triangle, zeros below).
@@ -366,19 +466,185 @@ __device__ __forceinline__ void retire(const KArgs& a, Prev& p) {
 //     reflector with the finished ones give G_b = U_b^T U_b, from which
 //     T_b (16 x 16 upper, Q_b = I - U_b T_b U_b^T) follows by the forward
 //     recurrence T(c,c) = tau_c, T(0:c-1,c) = -tau_c T(0:c-1,0:c-1) G(0:c-1,c).
+//     Waves 4-7, idle in the leaf, form T_b meanwhile, one column behind it.
 //  2. trailing: Q_b^T is applied to the column tiles right of the block with
-//     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W);
-//     T_b is formed by waves 4-7 during the leaf, one column behind it.
-//     Column tile J lives in registers of wave J % 8 for the whole kernel.
+//     three 16-wide MFMA products (W = U_b^T X, W = T_b^T W, X -= U_b W).
 // Record (FP64): V (nb x nb, column-major), then the nb/16 blocks T_b^T
 // (16 x 16 column-major) -- the same blocked compact-WY form the update
 // kernels apply.
 // ---------------------------------------------------------------------------
+
+// Step cc of the forward recurrence for T_b on waves 4-7: thread
+// (i, l) = (tid/16 - 16, tid%16) holds T(i, l); column cc is formed once
+// G(:, cc) is complete.
+__device__ __forceinline__ void t_step(double& til, int cc, const double* taus, const double* Gs, int lj, int lq) {
+    const int ti = lj - 16;
+    const double tcv = taus[cc];
+    const double gv = Gs[lq + 16 * cc];
+    const double sm = sum16((lq >= ti && lq < cc) ? til * gv : 0.0);
+    const double tic = cc < ti ? 0.0 : (cc == ti ? tcv : -tcv * sm);
+    if (lq == cc) til = tic;
+}
+
+// The 16 columns of leaf block B (one barrier per column).  lw selects the
+// role: the leaf waves factor (x: their leaf slots, r1: PAIR's R1 entry),
+// the other waves form T_b one column behind (til).  The column loop is
+// instantiated per block index B, which fixes at compile time where each
+// register slot s (rows lq + 16 s) lies relative to the block's diagonal
+// rows 16 B .. 16 B + 15: only slot B straddles the diagonal and needs
+// per-lane masks.  Slots that can hold no reflector entry (above the
+// diagonal block for GEQRT, below it for the triangle of TTQRT) are left out
+// of every step.
+template <int NB, int KIND, int B>
+__device__ __forceinline__ void leaf_columns(bool lw, double (&x)[NB / 16], double& r1, double& til, double* vbuf,
+                                             double* taus, double* Gs, int lj, int lq) {
+    constexpr int SR = NB / 16;
+    constexpr bool PAIR = KIND != K_GEQRT;
+    constexpr bool TT = KIND == K_TTQRT;
+    constexpr int S0 = PAIR ? 0 : B;        // live slots [S0, S1)
+    constexpr int S1 = TT ? B + 1 : SR;
+    constexpr int NL = S1 - S0;
+    // At nb = 256 the reflector is read again for the update instead of
+    // being held across the reduction (register budget).
+    constexpr bool REREAD = SR > 8;
+    for (int c = 0; c < 16; ++c) {
+        double* vb = vbuf + (c & 1) * NB;
+        if (lw && lj == c) {
+            // Reflector entry in slot s: rows below the diagonal (GEQRT),
+            // the whole tile (TSQRT) or rows up to it (TTQRT).
+            auto tail = [&](int s) {
+                if (!PAIR) return s > B || lq > c;
+                if (TT) return s < B || lq <= c;
+                return true;
+            };
+            // sum of squares in up to four partial sums
+            constexpr int NQ = NL < 4 ? NL : 4;
+            double q[NQ], al = 0.0;
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int s = S0 + k;
+                if (tail(s)) q[k % NQ] = fma(x[s], x[s], q[k % NQ]);
+            }
+            if (!PAIR && lq == c) al = x[B];
+#pragma unroll
+            for (int h = 1; h < NQ; h *= 2)
+#pragma unroll
+                for (int k = 0; k + h < NQ; k += 2 * h) q[k] += q[k + h];
+            if (PAIR && lq == c) al = r1;
+            const double ss = sum16(q[0]);
+            // alpha sits in the lane with row phase c of this column's 16
+            // lanes (lane 16 (c % 4) + c of the wave): read it there.
+            al = readlane64(al, 16 * (c & 3) + c);
+            double tau = 0.0, beta = al, scale = 0.0;
+            if (ss != 0.0) {
+                // tau = (beta - al) / beta and scale = 1 / (al - beta) from
+                // one reciprocal: with d = al - beta, 1 / (beta d) gives
+                // tau = -d^2 / (beta d) and scale = beta / (beta d).
+                const double nrm = refined_sqrt(fma(al, al, ss));
+                beta = al >= 0.0 ? -nrm : nrm;
+                const double d = al - beta;
+                const double inv = refined_rcp(beta * d);
+                tau = -(d * d) * inv;
+                scale = beta * inv;
+            }
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int s = S0 + k;
+                double vv;
+                if (!PAIR && s == B) {
+                    const bool t = lq > c, dg = lq == c;
+                    if (t) x[s] *= scale;
+                    if (dg) x[s] = beta;
+                    vv = t ? x[s] : (dg ? 1.0 : 0.0);
+                } else if (TT && s == B) {
+                    const bool t = lq <= c;
+                    if (t) x[s] *= scale;
+                    vv = t ? x[s] : 0.0;
+                } else {
+                    x[s] *= scale;
+                    vv = x[s];
+                }
+                vb[lq + 16 * s] = vv;
+            }
+            if (PAIR && lq == c) r1 = beta;
+            if (lq == 0) taus[c] = tau;
+        }
+        lds_barrier();
+        if (!lw) {
+            // G(:, c-1) was completed before this barrier
+            if (c > 0) t_step(til, c - 1, taus, Gs, lj, lq);
+        } else {
+            // the reflector and tau_c are read together (one LDS latency)
+            const double tc = taus[c];
+            double vv[SR];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
+            // tau_c is needed only after the dot product's reduction; holding
+            // it here keeps its read in the same batch as the reflector's
+            // instead of after the reduction.
+            asm volatile("" ::"v"(tc));
+            // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
+            // every T entry that G(:, c) feeds.
+            if (lj != c) {
+                double dp[2] = {0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
+                double d = dp[0] + dp[1];
+                if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                if (REREAD) SCHED_FENCE();
+                d = sum16(d);
+                if (lj > c) {
+                    const double wv = tc * d;
+                    if (REREAD) {
+                        SCHED_FENCE();
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vb[lq + 16 * (S0 + k)];
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
+                    }
+                    if (PAIR && lq == c) r1 -= wv;
+                } else if (lq == 0) {
+                    Gs[lj + 16 * c] = d;            // u_lj . u_c
+                }
+            }
+        }
+    }
+}
+
+// Dispatch of leaf block b (runtime) to its instantiation, for the blocks
+// BASE .. BASE + COUNT - 1 (COUNT <= 8).
+template <int NB, int KIND, int BASE, int COUNT>
+__device__ __forceinline__ void leaf_block(int b, bool lw, double (&x)[NB / 16], double& r1, double& til,
+                                           double* vbuf, double* taus, double* Gs, int lj, int lq) {
+    constexpr int MT = NB / 16;
+    auto go = [&](auto bc) {
+        constexpr int B = decltype(bc)::value;
+        if constexpr (B < MT && B < BASE + COUNT) leaf_columns<NB, KIND, B>(lw, x, r1, til, vbuf, taus, Gs, lj, lq);
+    };
+    if (b < BASE || b >= BASE + COUNT) return;      // uniform
+    switch (b - BASE) {
+        case 0: go(std::integral_constant<int, BASE + 0>{}); break;
+        case 1: go(std::integral_constant<int, BASE + 1>{}); break;
+        case 2: go(std::integral_constant<int, BASE + 2>{}); break;
+        case 3: go(std::integral_constant<int, BASE + 3>{}); break;
+        case 4: go(std::integral_constant<int, BASE + 4>{}); break;
+        case 5: go(std::integral_constant<int, BASE + 5>{}); break;
+        case 6: go(std::integral_constant<int, BASE + 6>{}); break;
+        default: go(std::integral_constant<int, BASE + 7>{}); break;
+    }
+}
+
+// Panel for nb <= 128: the whole tile is register-resident, column tile J
+// on wave J for the whole kernel; all eight waves apply the trailing
+// products.
 template <int NB, int KIND, bool CO>
-__device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
+__device__ __forceinline__ void panel_resident(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
     using S = Shape<NB>;
     constexpr int MT = S::MT, LDL = S::LDL;
-    constexpr int OWN = (MT + 7) / 8;       // column tiles per wave
+    static_assert(MT <= 8, "one column tile per wave");
     constexpr int SR = NB / 16;             // leaf rows per thread
     constexpr bool PAIR = KIND != K_GEQRT;
     constexpr bool TT = KIND == K_TTQRT;
@@ -390,7 +656,8 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     double* R1s = TbT + 256;                // PAIR: R1(16b + lq, 16b + lj) of the next block, per leaf thread
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int lj = tid >> 4, lq = tid & 15; // leaf column, row phase
-    const bool lw = tid < 256;              // waves 0-3 run the leaf and form T_b
+    const bool lw = tid < 256;              // waves 0-3 run the leaf, waves 4-7 form T_b
+    const bool own = w < MT;                // the wave holds column tile w
 
     const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
     const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
@@ -398,10 +665,8 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
     double* gV = rec;
     double* gTt = rec + NB * NB;
 
-    d4 xt[OWN][MT];
-#pragma unroll
-    for (int o = 0; o < OWN; ++o)
-        if (w + 8 * o < MT) load_slice<MT>(TX, 16 * (w + 8 * o), xt[o]);
+    d4 xt[MT];
+    if (own) load_slice<MT>(TX, 16 * w, xt);
     // R1's row block b is changed by no block before b (the reflectors of
     // block b' touch rows of block b' only), so the diagonal entries the leaf
     // of block b + 1 starts from are read during block b, before that block's
@@ -413,172 +678,31 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 
     for (int b = 0; b < MT; ++b) {
         // Column tile b goes to the leaf buffer.
-        if (w == (b & 7)) {
+        if (w == b) {
 #pragma unroll
-            for (int o = 0; o < OWN; ++o)
-                if (o == (b >> 3)) {
+            for (int i = 0; i < MT; ++i)
 #pragma unroll
-                    for (int i = 0; i < MT; ++i)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) Lf[(16 * i + 4 * r + g) + j * LDL] = xt[o][i][r];
-                }
+                for (int r = 0; r < 4; ++r) Lf[(16 * i + 4 * r + g) + j * LDL] = xt[i][r];
         }
         if (lw) Gs[tid] = 0.0;
         lds_barrier();
 
-        // 1. Leaf.
+        // 1. Leaf (waves 0-3), T_b one column behind (waves 4-7).
         double x[SR];
-        double r1 = 0.0;                    // PAIR: R1(16b + lq, 16b + lj)
-        // Waves 4-7, idle in the leaf, form T_b meanwhile by the forward
-        // recurrence T(c,c) = tau_c, T(i,c) = -tau_c sum_{l=i}^{c-1} T(i,l) G(l,c):
-        // thread (i, l) = (tid/16 - 16, tid%16) holds T(i, l), and column c
-        // is formed once G(:, c) is complete, one column behind the leaf.
-        double til = 0.0;
-        auto tstep = [&](int cc) {
-            const int ti = lj - 16;
-            const double tcv = taus[cc];
-            const double gv = Gs[lq + 16 * cc];
-            const double sm = sum16((lq >= ti && lq < cc) ? til * gv : 0.0);
-            const double tic = cc < ti ? 0.0 : (cc == ti ? tcv : -tcv * sm);
-            if (lq == cc) til = tic;
-        };
+        double r1 = 0.0, til = 0.0;
         if (lw) {
 #pragma unroll
             for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
             if (PAIR) r1 = R1s[tid];
         }
-        // The column loop is instantiated per block index B, which fixes at
-        // compile time where each register slot s (rows lq + 16 s) lies
-        // relative to the block's diagonal rows 16 B .. 16 B + 15: only slot B
-        // straddles the diagonal and needs per-lane masks.  Slots that can
-        // hold no reflector entry (above the diagonal block for GEQRT, below
-        // it for the triangle of TTQRT) are left out of every step.
-        auto leaf = [&](auto bconst) {
-            constexpr int B = decltype(bconst)::value;
-            if constexpr (B < MT) {
-                constexpr int S0 = PAIR ? 0 : B;        // live slots [S0, S1)
-                constexpr int S1 = TT ? B + 1 : SR;
-                constexpr int NL = S1 - S0;
-                for (int c = 0; c < 16; ++c) {
-                    double* vb = vbuf + (c & 1) * NB;
-                    if (lw && lj == c) {
-                        // Reflector entry in slot s: rows below the diagonal
-                        // (GEQRT), the whole tile (TSQRT) or rows up to it (TTQRT).
-                        auto tail = [&](int s) {
-                            if (!PAIR) return s > B || lq > c;
-                            if (TT) return s < B || lq <= c;
-                            return true;
-                        };
-                        double q[NL], al = 0.0;
-#pragma unroll
-                        for (int k = 0; k < NL; ++k) {
-                            const int s = S0 + k;
-                            q[k] = tail(s) ? x[s] * x[s] : 0.0;
-                        }
-                        if (!PAIR && lq == c) al = x[B];
-#pragma unroll
-                        for (int h = 1; h < NL; h *= 2)
-#pragma unroll
-                            for (int k = 0; k + h < NL; k += 2 * h) q[k] += q[k + h];
-                        if (PAIR && lq == c) al = r1;
-                        const double ss = sum16(q[0]);
-                        // alpha sits in the lane with row phase c of this column's
-                        // 16 lanes (lane 16 (c % 4) + c of the wave): read it there.
-                        al = readlane64(al, 16 * (c & 3) + c);
-                        double tau = 0.0, beta = al, scale = 0.0;
-                        if (ss != 0.0) {
-                            // tau = (beta - al) / beta and scale = 1 / (al - beta)
-                            // from one reciprocal: with d = al - beta,
-                            // 1 / (beta d) gives tau = -d^2 / (beta d) and scale = beta / (beta d).
-                            const double nrm = refined_sqrt(fma(al, al, ss));
-                            beta = al >= 0.0 ? -nrm : nrm;
-                            const double d = al - beta;
-                            const double inv = refined_rcp(beta * d);
-                            tau = -(d * d) * inv;
-                            scale = beta * inv;
-                        }
-#pragma unroll
-                        for (int k = 0; k < NL; ++k) {
-                            const int s = S0 + k;
-                            double vv;
-                            if (!PAIR && s == B) {
-                                const bool t = lq > c, dg = lq == c;
-                                if (t) x[s] *= scale;
-                                if (dg) x[s] = beta;
-                                vv = t ? x[s] : (dg ? 1.0 : 0.0);
-                            } else if (TT && s == B) {
-                                const bool t = lq <= c;
-                                if (t) x[s] *= scale;
-                                vv = t ? x[s] : 0.0;
-                            } else {
-                                x[s] *= scale;
-                                vv = x[s];
-                            }
-                            vb[lq + 16 * s] = vv;
-                        }
-                        if (PAIR && lq == c) r1 = beta;
-                        if (lq == 0) taus[c] = tau;
-                    }
-                    lds_barrier();
-                    if (!lw) {
-                        // G(:, c-1) was completed before this barrier
-                        if (c > 0) tstep(c - 1);
-                    } else {
-                        // the reflector and tau_c are read together (one LDS latency)
-                        const double tc = taus[c];
-                        double vv[SR];
-#pragma unroll
-                        for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
-                        // tau_c is needed only after the dot product's reduction;
-                        // holding it here keeps its read in the same batch as the
-                        // reflector's instead of after the reduction.
-                        asm volatile("" ::"v"(tc));
-                        // tau_c = 0 (H_c = I) needs no branch: it zeroes the update and
-                        // every T entry that G(:, c) feeds.
-                        if (lj != c) {
-                            double dp[2] = {0.0, 0.0};
-#pragma unroll
-                            for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
-                            double d = dp[0] + dp[1];
-                            if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
-                            d = sum16(d);
-                            if (lj > c) {
-                                const double wv = tc * d;
-#pragma unroll
-                                for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
-                                if (PAIR && lq == c) r1 -= wv;
-                            } else if (lq == 0) {
-                                Gs[lj + 16 * c] = d;            // u_lj . u_c
-                            }
-                        }
-                    }
-                }
-            }
-        };
-        static_assert(MT <= 8, "block index dispatch covers nb <= 128");
-        switch (b) {
-            case 0: leaf(std::integral_constant<int, 0>{}); break;
-            case 1: leaf(std::integral_constant<int, 1>{}); break;
-            case 2: leaf(std::integral_constant<int, 2>{}); break;
-            case 3: leaf(std::integral_constant<int, 3>{}); break;
-            case 4: leaf(std::integral_constant<int, 4>{}); break;
-            case 5: leaf(std::integral_constant<int, 5>{}); break;
-            case 6: leaf(std::integral_constant<int, 6>{}); break;
-            default: leaf(std::integral_constant<int, 7>{}); break;
-        }
+        leaf_block<NB, KIND, 0, MT>(b, lw, x, r1, til, vbuf, taus, Gs, lj, lq);
         // Loads ahead of the leaf outputs' stores: the next block's diagonal
         // entry of R1 and this block's rows of R1 in the trailing tiles.
         double r1n = 0.0;
         if (PAIR && lw && b + 1 < MT) r1n = T1.get(16 * (b + 1) + lq, 16 * (b + 1) + lj);
-        bool act[OWN];
-        d4 R1b[OWN], W[OWN];
-#pragma unroll
-        for (int o = 0; o < OWN; ++o) {
-            const int J = w + 8 * o;
-            act[o] = J < MT && J > b;
-            R1b[o] = d4{0.0, 0.0, 0.0, 0.0};
-            if (PAIR && act[o]) R1b[o] = load16(T1, 16 * b, 16 * J);
-        }
+        const bool act = own && w > b;
+        d4 R1b = {0.0, 0.0, 0.0, 0.0}, W;
+        if (PAIR && act) R1b = load16(T1, 16 * b, 16 * w);
         // Leaf outputs, each thread on the leaf slots it read: explicit U_b
         // into the leaf buffer and the record, R (GEQRT) or zeros (TS/TT)
         // into the matrix.
@@ -601,8 +725,7 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
 
         // 2. Trailing update of the column tiles right of block b:
         // W = R1 + U_b^T X, then W = T_b^T W, then X -= U_b W.
-#pragma unroll
-        for (int o = 0; o < OWN; ++o) W[o] = R1b[o];
+        W = R1b;
         double la[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) la[r] = Lf[(4 * r + g) + j * LDL];
@@ -614,12 +737,10 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
                 for (int r = 0; r < 4; ++r) ln[r] = Lf[(16 * (i + 1) + 4 * r + g) + j * LDL];
             }
             const bool rows = (PAIR || i >= b) && (!TT || i <= b);
+            if (act && rows) {
 #pragma unroll
-            for (int o = 0; o < OWN; ++o)
-                if (act[o] && rows) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) W[o] = mfma(la[r], xt[o][i][r], W[o]);
-                }
+                for (int r = 0; r < 4; ++r) W = mfma(la[r], xt[i][r], W);
+            }
             SCHED_FENCE();
             if (i + 1 < MT) {
 #pragma unroll
@@ -627,20 +748,18 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             }
         }
         if (!lw) {
-            tstep(15);
+            t_step(til, 15, taus, Gs, lj, lq);
             TbT[lq + 16 * (lj - 16)] = til;     // T(i, l)
             gstore<CO>(gTt + 256 * b + (tid - 256), til);
         }
         lds_barrier();
+        if (act) {
+            d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int o = 0; o < OWN; ++o)
-            if (act[o]) {
-                d4 W2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[o][r], W2);
-                if (PAIR) store16<CO>(T1, 16 * b, 16 * (w + 8 * o), R1b[o] - W2);
-                W[o] = W2;
-            }
+            for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
+            if (PAIR) store16<CO>(T1, 16 * b, 16 * w, R1b - W2);
+            W = W2;
+        }
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
             if (!PAIR && i < b) continue;
@@ -648,43 +767,188 @@ __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double*
             double lu[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) lu[r] = -Lf[(16 * i + j) + (4 * r + g) * LDL];
+            if (act) {
 #pragma unroll
-            for (int o = 0; o < OWN; ++o)
-                if (act[o]) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) xt[o][i] = mfma(lu[r], W[o][r], xt[o][i]);
-                }
+                for (int r = 0; r < 4; ++r) xt[i] = mfma(lu[r], W[r], xt[i]);
+            }
             SCHED_FENCE();
         }
         lds_barrier();
     }
 }
 
+// Panel for nb = 256 (16 column tiles of 256 x 16; one tile takes half of a
+// wave's register budget, so the tile cannot stay resident next to the
+// leaf).  The leaf works on an LDS copy of its column tile as above; the
+// trailing tiles are streamed instead: in block b each wave loads the tiles
+// J > b it owns (J = w and J = w + 8, a fixed assignment), applies Q_b^T
+// and stores them back.  Every lane reads back only the elements it stored
+// itself, so the stores need no fence.  Tile b + 1 goes to the second leaf
+// buffer in LDS instead of memory, where the next leaf reads it.
+template <int NB, int KIND, bool CO>
+__device__ __forceinline__ void panel_stream(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
+    using S = Shape<NB>;
+    constexpr int MT = S::MT, LDL = S::LDL;
+    static_assert(MT == 16, "two tiles per wave");
+    constexpr int SR = NB / 16;
+    constexpr bool PAIR = KIND != K_GEQRT;
+    constexpr bool TT = KIND == K_TTQRT;
+    double* Lf0 = lds;                      // leaf buffers: NB x 16, stride LDL, alternating by block
+    double* vbuf = lds + 32 * LDL;
+    double* taus = vbuf + 2 * NB;
+    double* Gs = taus + 16;
+    double* TbT = Gs + 256;
+    double* R1s = TbT + 256;
+    const int tid = threadIdx.x, lane = tid & 63, j = lane & 15, g = lane >> 4;
+    const int lj = tid >> 4, lq = tid & 15;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool lw = w < 4;                  // waves 0-3 run the leaf, waves 4-7 form T_b
+
+    const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
+    const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
+    double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
+    double* gV = rec;
+    double* gTt = rec + NB * NB;
+
+    // column tile 0 into the first leaf buffer (8 elements per thread)
+#pragma unroll
+    for (int k = 0; k < NB * 16 / NT; ++k) {
+        const int e = tid + NT * k, r = e % NB, c = e / NB;
+        Lf0[r + c * LDL] = TX.get(r, c);
+    }
+    if (PAIR && lw) R1s[tid] = T1.get(lq, lj);
+    retire(a, prev);
+
+    for (int b = 0; b < MT; ++b) {
+        double* Lf = Lf0 + (b & 1) * 16 * LDL;
+        double* Ln = Lf0 + ((b + 1) & 1) * 16 * LDL;
+        if (lw) Gs[tid] = 0.0;
+        lds_barrier();
+
+        // 1. Leaf (waves 0-3), T_b one column behind (waves 4-7).
+        double x[SR];
+        double r1 = 0.0, til = 0.0;
+        if (lw) {
+#pragma unroll
+            for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
+            if (PAIR) r1 = R1s[tid];
+            leaf_block<NB, KIND, 0, 8>(b, true, x, r1, til, vbuf, taus, Gs, lj, lq);
+            leaf_block<NB, KIND, 8, 8>(b, true, x, r1, til, vbuf, taus, Gs, lj, lq);
+        } else {
+            leaf_block<NB, KIND, 0, 8>(b, false, x, r1, til, vbuf, taus, Gs, lj, lq);
+            leaf_block<NB, KIND, 8, 8>(b, false, x, r1, til, vbuf, taus, Gs, lj, lq);
+        }
+        if (lw) {
+            double r1n = 0.0;
+            if (PAIR && b + 1 < MT) r1n = T1.get(16 * (b + 1) + lq, 16 * (b + 1) + lj);
+            const int col = 16 * b + lj;
+#pragma unroll
+            for (int s = 0; s < SR; ++s) {
+                const int row = lq + 16 * s;
+                double vv;
+                if (PAIR) vv = (TT && row > col) ? 0.0 : x[s];
+                else vv = row > col ? x[s] : (row == col ? 1.0 : 0.0);
+                Lf[row + lj * LDL] = vv;
+                gstore<CO>(gV + row + (int64_t)col * NB, vv);
+                TX.put<CO>(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
+            }
+            if (PAIR) T1.put<CO>(16 * b + lq, 16 * b + lj, r1);
+            if (PAIR && b + 1 < MT) R1s[tid] = r1n;
+        }
+        lds_barrier();
+
+        // 2. Trailing update of the tiles right of block b, at most two per
+        // wave: W = R1 + U_b^T X, W = T_b^T W, X -= U_b W.
+        auto tile_step = [&](int J, bool act, bool first) {
+            SCHED_FENCE();
+            d4 xt[MT];
+            d4 R1b = {0.0, 0.0, 0.0, 0.0};
+            if (act) {
+                load_slice<MT>(TX, 16 * J, xt);
+                if (PAIR) R1b = load16(T1, 16 * b, 16 * J);
+            }
+            d4 W = R1b;
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const bool rows = (PAIR || i >= b) && (!TT || i <= b);
+                if (act && rows) {
+                    double la[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) la[r] = Lf[(16 * i + 4 * r + g) + j * LDL];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) W = mfma(la[r], xt[i][r], W);
+                }
+                if (i & 1) SCHED_FENCE();
+            }
+            if (first) {
+                if (!lw) {
+                    t_step(til, 15, taus, Gs, lj, lq);
+                    TbT[lq + 16 * (lj - 16)] = til;     // T(i, l)
+                    gstore<CO>(gTt + 256 * b + (tid - 256), til);
+                }
+                lds_barrier();
+            }
+            if (act) {
+                d4 W2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
+                if (PAIR) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    if (!PAIR && i < b) continue;
+                    if (TT && i > b) continue;
+                    double lu[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) lu[r] = -Lf[(16 * i + j) + (4 * r + g) * LDL];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xt[i] = mfma(lu[r], W2[r], xt[i]);
+                    if (i & 1) SCHED_FENCE();
+                }
+                if (J == b + 1) {
+                    // the next leaf's column tile
+#pragma unroll
+                    for (int i = 0; i < MT; ++i)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Ln[(16 * i + 4 * r + g) + j * LDL] = xt[i][r];
+                } else {
+                    store_slice<CO, MT>(TX, 16 * J, xt);
+                }
+            }
+        };
+        // Round 0 takes tile b + 1 (wave (b + 1) % 8) and every wave's
+        // first remaining tile; round 1 the second tile of the waves that
+        // still own two.
+        // (a loop kept rolled: the two rounds' tiles are never live together)
+#pragma unroll 1
+        for (int k = 0; k < 2; ++k) {
+            const int J = k == 0 ? (w > b ? w : w + 8) : w + 8;
+            const bool act = (k == 0 || w > b) && J < MT && J > b;
+            tile_step(J, act, k == 0);
+        }
+        lds_barrier();
+    }
+}
+
+template <int NB, int KIND, bool CO>
+__device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
+    if constexpr (NB <= 128) panel_resident<NB, KIND, CO>(a, tk, lds, prev);
+    else panel_stream<NB, KIND, CO>(a, tk, lds, prev);
+}
+
 // ---------------------------------------------------------------------------
-// Update kernels: UNMQR, TSMQR, TTMQR (Table 1) on the whole trailing tile
-// (or tile pair).  Wave w owns the 16 logical columns 16 w .. 16 w + 15 of C2
-// (and C1); waves past the tile's width only stage and synchronize.  Each
-// applies the nb/16 blocks of the record in order (block b+1 is fetched from
-// memory while block b is applied, then staged in LDS for all eight waves):
-//   W = C1(block-row b) + V_b^T C2     (UNMQR: no C1)
-//   W = T_b^T W
-//   C1(block-row b) -= W,   C2 -= V_b W
-// which is Q^T [C1; C2] for Q = Q_0 Q_1 ... (Section 3.2).  Zero 16 x 16
-// blocks of V are skipped: V is unit lower triangular after GEQRT and upper
-// triangular after TTQRT.  HQ applies Q itself (used to form Q C and P C
-// from the records): the blocks in reverse order, each with T_b instead of
-// T_b^T.
+// Update kernels: UNMQR, TSMQR, TTMQR (Table 1) on a strip of the trailing
+// tile (or tile pair): the whole tile for nb <= 128, a 128-column half for
+// nb = 256.  Wave w owns the 16 logical columns c0 = part * NS + 16 w ..
+// c0 + 15 of C2 (and C1); waves past the tile's width only stage and
+// synchronize.  All nb/16 blocks of the record are applied (apply_blocks).
 // ---------------------------------------------------------------------------
 template <int NB, int KIND, bool CO, bool HQ>
 __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
                                        int* sch) {
     constexpr int MT = NB / 16;
-    constexpr int NS = NB;                   // the whole tile: one 16-column slice per wave
-    constexpr int LDV = NB + 1;
-    constexpr int BUF = 16 * LDV + 256;       // V_b (NB x 16, stride LDV) then T_b^T (16 x 16)
-    constexpr int PRE = 16 * NB / NT + 1;     // staged doubles per thread and block
+    constexpr int NS = NB < 128 ? NB : 128;  // strip width: one 16-column slice per wave
     constexpr bool HASC1 = KIND != K_UNMQR;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
+    const int tid = threadIdx.x, w = tid >> 6;
     const int c0 = part * NS + 16 * w;
     const TileView T2 = view(a, tk, tk.r2, tk.c2, NB);
     const TileView T1 = HASC1 ? view(a, tk, tk.r1, tk.c1, NB) : T2;
@@ -692,73 +956,9 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     const bool active = 16 * w < NS && c0 < T2.vc;
     const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
 
-    // Block b of the record: V(:, 16b..16b+15) is contiguous (column-major),
-    // T_b^T follows the nb x nb matrix.  Thread t stages elements t + NT k of
-    // V_b and element t of T_b^T (t < 256).
-    auto fetch = [&](int b, double (&pre)[PRE]) {
-#pragma unroll
-        for (int k = 0; k < PRE - 1; ++k) pre[k] = rec.ld(8 * (tid + NT * k), 8 * (16 * b * NB));
-        pre[PRE - 1] = tid < 256 ? rec.ld(8 * tid, 8 * (NB * NB + 256 * b)) : 0.0;
-    };
-    auto stage = [&](int buffer, const double (&pre)[PRE]) {
-        double* buf = lds + buffer * BUF;
-#pragma unroll
-        for (int k = 0; k < PRE - 1; ++k) {
-            const int e = tid + NT * k;
-            buf[(e % NB) + (e / NB) * LDV] = pre[k];
-        }
-        if (tid < 256) buf[16 * LDV + tid] = pre[PRE - 1];
-    };
-    auto blk = [](int step) { return HQ ? MT - 1 - step : step; };
-
     d4 c2[MT];
     if (active) load_slice<MT>(T2, c0, c2);
-    double pre[PRE];
-    fetch(blk(0), pre);
-    retire(a, prev);
-    stage(0, pre);
-    d4 C1n = {0.0, 0.0, 0.0, 0.0};
-    if (HASC1 && active) C1n = load16(T1, 16 * blk(0), c0);
-    lds_barrier();
-#pragma unroll
-    for (int st = 0; st < MT; ++st) {
-        const int b = blk(st);
-        const double* Vs = lds + (st & 1) * BUF;
-        const double* Ts = Vs + 16 * LDV;
-        if (st + 1 < MT) fetch(blk(st + 1), pre);
-        const d4 C1b = C1n;
-        if (HASC1 && active && st + 1 < MT) C1n = load16(T1, 16 * blk(st + 1), c0);
-        if (active) {
-            // Two accumulators halve the dependent-MFMA chain of W.
-            d4 Wp[2] = {C1b, {0.0, 0.0, 0.0, 0.0}};
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                if (KIND == K_UNMQR && i < b) continue;
-                if (KIND == K_TTMQR && i > b) continue;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    Wp[r & 1] = mfma(Vs[(16 * i + 4 * r + g) + j * LDV], c2[i][r], Wp[r & 1]);
-            }
-            const d4 W = Wp[0] + Wp[1];
-            d4 W2 = {0.0, 0.0, 0.0, 0.0};
-            // Ts holds T_b^T column-major: T_b(k, i) at i + 16 k.
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                W2 = mfma(-(HQ ? Ts[(4 * r + g) + 16 * j] : Ts[j + 16 * (4 * r + g)]), W[r], W2);
-            // W2 holds -T_b^T W: negating the 4 T operands spares negating
-            // the 32 V operands of the update below.
-            if (HASC1) store16<CO>(T1, 16 * b, c0, C1b + W2);
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                if (KIND == K_UNMQR && i < b) continue;
-                if (KIND == K_TTMQR && i > b) continue;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) c2[i] = mfma(Vs[(16 * i + j) + (4 * r + g) * LDV], W2[r], c2[i]);
-            }
-        }
-        if (st + 1 < MT) stage((st + 1) & 1, pre);
-        lds_barrier();
-    }
+    apply_blocks<NB, MT, KIND, CO, HQ>(rec, T1, c0, active, &c2[0], lds, a, prev);
     if (sch != nullptr) take_next(a, sch);
     if (active) store_slice<CO, MT>(T2, c0, c2);
 }
@@ -822,7 +1022,7 @@ template <int NB, int KIND, bool CO, bool SPLIT>
 __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int part, double* lds, Prev& prev,
                                          int* sch) {
     constexpr int MT = NB / 16;
-    constexpr int NS = NB;                   // the whole tile: one 16-column slice per wave
+    constexpr int NS = NB < 128 ? NB : 128;  // strip width: one 16-column slice per wave
     constexpr int LDV = NB + 1;
     constexpr int PL = 16 * LDV + 256;        // floats per plane: V_b (NB x 16) then T_b^T
     constexpr int BUF = (SPLIT ? 2 : 1) * PL; // hi plane [, lo plane]
@@ -1047,6 +1247,7 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
     }
 }
 
+#ifdef BB_KERNELS_COMMON
 __global__ void init_kernel(int32_t* deps, const int32_t* ndeps, int32_t ntasks, int32_t* ctrl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < CTRL_WORDS) ctrl[i] = 0;
@@ -1078,7 +1279,7 @@ hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, 
     return hipGetLastError();
 }
 
-bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128; }
+bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128 || nb == 256; }
 
 // Workspace of bb_execute_noalloc: a file-scope device array, one copy per
 // device for the life of the process.  Host code never passes the array's
@@ -1108,29 +1309,54 @@ hipError_t noalloc_scratch(void** ptr, size_t* bytes) {
     return hipSuccess;
 }
 
-#define BB_DISPATCH(KERNEL, GRID, ...)                                                   \
-    switch (nb * 4 + prec) {                                                             \
-    case 32 * 4 + 0: hipLaunchKernelGGL((KERNEL<32, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 32 * 4 + 2: hipLaunchKernelGGL((KERNEL<32, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 32 * 4 + 3: hipLaunchKernelGGL((KERNEL<32, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 64 * 4 + 0: hipLaunchKernelGGL((KERNEL<64, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 64 * 4 + 2: hipLaunchKernelGGL((KERNEL<64, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 64 * 4 + 3: hipLaunchKernelGGL((KERNEL<64, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break;   \
-    case 128 * 4 + 0: hipLaunchKernelGGL((KERNEL<128, 0>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
-    case 128 * 4 + 2: hipLaunchKernelGGL((KERNEL<128, 2>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
-    case 128 * 4 + 3: hipLaunchKernelGGL((KERNEL<128, 3>), GRID, dim3(NT), 0, s, __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                \
+#endif  // BB_KERNELS_COMMON
+
+template <int NB, int PREC>
+hipError_t launch_level_np(const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s) {
+    hipLaunchKernelGGL((level_kernel<NB, PREC>), dim3(count), dim3(NT), 0, s, a, unit_base);
+    return hipGetLastError();
+}
+
+template <int NB, int PREC>
+hipError_t launch_persistent_np(const KArgs& a, int32_t workgroups, hipStream_t s) {
+    hipLaunchKernelGGL((persistent_kernel<NB, PREC>), dim3(workgroups), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// This file is compiled once per (tile size, arithmetic) pair (BB_KERNELS_NB,
+// BB_KERNELS_PREC: that pair's kernels, the translation units built in
+// parallel) and once for the size-independent part (BB_KERNELS_COMMON).
+#if defined(BB_KERNELS_NB) && defined(BB_KERNELS_PREC)
+template hipError_t launch_level_np<BB_KERNELS_NB, BB_KERNELS_PREC>(const KArgs&, int32_t, int32_t, hipStream_t);
+template hipError_t launch_persistent_np<BB_KERNELS_NB, BB_KERNELS_PREC>(const KArgs&, int32_t, hipStream_t);
+#endif
+
+#ifdef BB_KERNELS_COMMON
+#define BB_NP_CASES(F, ...)                                                        \
+    switch (nb * 4 + prec) {                                                       \
+    case 32 * 4 + 0: return F<32, 0>(__VA_ARGS__);                                 \
+    case 32 * 4 + 2: return F<32, 2>(__VA_ARGS__);                                 \
+    case 32 * 4 + 3: return F<32, 3>(__VA_ARGS__);                                 \
+    case 64 * 4 + 0: return F<64, 0>(__VA_ARGS__);                                 \
+    case 64 * 4 + 2: return F<64, 2>(__VA_ARGS__);                                 \
+    case 64 * 4 + 3: return F<64, 3>(__VA_ARGS__);                                 \
+    case 128 * 4 + 0: return F<128, 0>(__VA_ARGS__);                               \
+    case 128 * 4 + 2: return F<128, 2>(__VA_ARGS__);                               \
+    case 128 * 4 + 3: return F<128, 3>(__VA_ARGS__);                               \
+    case 256 * 4 + 0: return F<256, 0>(__VA_ARGS__);                               \
+    case 256 * 4 + 2: return F<256, 2>(__VA_ARGS__);                               \
+    case 256 * 4 + 3: return F<256, 3>(__VA_ARGS__);                               \
+    default: return hipErrorInvalidValue;                                          \
     }
 
 hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    BB_DISPATCH(level_kernel, dim3(count), a, unit_base)
-    return hipGetLastError();
+    BB_NP_CASES(launch_level_np, a, unit_base, count, s)
 }
 
 hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s) {
-    BB_DISPATCH(persistent_kernel, dim3(workgroups), a)
-    return hipGetLastError();
+    BB_NP_CASES(launch_persistent_np, a, workgroups, s)
 }
+#endif  // BB_KERNELS_COMMON
 
 }  // namespace bbk

@@ -39,9 +39,10 @@ struct KArgs {
                              // {ready-wait start, run start, run end, workgroup}
 };
 
-// Update strip width (columns of the logical C tile per work unit): the whole
-// tile, one 16-column slice per wave of the 512-thread workgroup.
-inline int strip_width(int nb) { return nb; }
+// Update strip width (columns of the logical C tile per work unit): one
+// 16-column slice per wave of the 512-thread workgroup, so the whole tile up
+// to nb = 128 and a 128-column half at nb = 256.
+inline int strip_width(int nb) { return nb < 128 ? nb : 128; }
 
 // One V/T record: V (nb x nb) and nb/16 blocks T_b^T (16 x 16).
 inline int64_t record_doubles(int nb) { return 1LL * nb * nb + 16LL * nb; }
@@ -57,6 +58,12 @@ hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, 
 // prec: 0 = FP64, 2 = FP32-MFMA updates, 3 = split-FP32 updates (bidiag.h's BB_F64*).
 hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
 hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s);
+// The same for one (tile size, arithmetic) pair (each pair's kernels are
+// built in their own translation unit).
+template <int NB, int PREC>
+hipError_t launch_level_np(const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
+template <int NB, int PREC>
+hipError_t launch_persistent_np(const KArgs& a, int32_t workgroups, hipStream_t s);
 bool nb_supported(int nb);
 
 // Workspace for callers that cannot allocate: the current device's copy of a

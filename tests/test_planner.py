@@ -331,3 +331,22 @@ def test_batch_argument_errors():
     assert L.bb_batch_execute(p._h, None, v8, v8, vt.value, v8, ws.value, None) == -2
     assert L.bb_batch_execute(p._h, v8, v8, v8, vt.value - 8, v8, ws.value, None) == 6
     assert L.bb_batch_execute(p._h, v8, v8, v8, vt.value, v8, ws.value - 8, None) == 6
+
+
+def test_nb256_plan_splits_updates_in_halves():
+    """At nb = 256 an update unit covers a 128-column half of a tile: every
+    update task is two work units, every panel one; records keep the nb x nb
+    + nb/16 blocks format."""
+    p = bb.Plan(1100, 700, 256, "greedy", "bidiag")
+    st = p.stats()
+    k = st["count_by_kind"]
+    panels = k["GEQRT"] + k["TSQRT"] + k["TTQRT"]
+    updates = k["UNMQR"] + k["TSMQR"] + k["TTMQR"]
+    assert st["p"] == 5 and st["q"] == 3
+    assert st["nunits"] == panels + 2 * updates
+    vt, _ = p.workspace()
+    assert vt == st["nslots"] * (256 * 256 + 16 * 256) * 8
+    for nb in (16, 96, 512):
+        h = ctypes.c_void_p()
+        opts = bb.make_opts()
+        assert bb.lib().bb_plan_create(ctypes.byref(h), 2000, 1000, nb, 2, 0, 0, ctypes.byref(opts)) == 1
