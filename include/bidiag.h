@@ -7,6 +7,11 @@
  *
  *     B = Q^T A P,     B(i,j) = 0 unless 0 <= j - i <= nb,   rows >= n zero,
  *
+ * For m < n the reduction is that of A^T (Section 3.6): A^T = Q' B' P'^T,
+ * so A = Q B P^T with Q = P', P = Q' and the lower band form B = B'^T,
+ * B(i,j) = 0 unless 0 <= i - j <= nb, columns >= m zero.  The graph is that
+ * of A^T, run on A's own storage through transposed tile views.
+ *
  * by alternating QR and LQ tile-panel eliminations along a reduction tree:
  *   BiDiag   : QR(1); LQ(1); QR(2); ...; QR(q-1); LQ(q-1); QR(q)   (Section 3.4)
  *   R-BiDiag : QR(p,q); LQ(1); QR(2); ...; LQ(q-1); QR(q)           (Section 3.5)
@@ -54,7 +59,7 @@ extern "C" {
 
 /* ---- error codes ------------------------------------------------------- */
 #define BB_OK        0
-#define BB_ENOTSUP   1   /* valid but unsupported request (e.g. m < n, nb not in {32,64,128,256}) */
+#define BB_ENOTSUP   1   /* valid but unsupported request (e.g. nb not in {32,64,128,256}) */
 #define BB_EHIP      2   /* a HIP runtime call failed */
 #define BB_ETIMEOUT  3   /* the device scheduler's watchdog fired (no progress) */
 #define BB_EDAG      4   /* the task graph failed validation on the host */
@@ -66,8 +71,12 @@ extern "C" {
 enum { BB_FLATTS = 0, BB_FLATTT = 1, BB_GREEDY = 2, BB_AUTO = 3 };
 /* Algorithms: Section 3.4 (BiDiag), Section 3.5 (R-BiDiag).  BB_QRONLY runs
  * only the tiled QR factorization QR(p,q) of Algorithm 1 (A is overwritten by
- * R, rows >= n zero). */
-enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2 };
+ * R, rows >= n zero).  BB_THREESTEP is the three-step reduction of Section
+ * 4.5: BiDiag steps QR(k); LQ(k) for k < s, then R-BiDiag on the trailing
+ * (p-s) x (q-s) tiles; s is bb_opts.switch_step when positive, else the
+ * first k whose trailing tiles satisfy p - k >= delta (q - k) (the
+ * BiDiag/R-BiDiag switching point of Section 4.3.4), q if none. */
+enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2, BB_THREESTEP = 3 };
 /* Arithmetic.  BB_F64 computes everything in FP64.  The two other modes keep
  * the matrix, the panels (reflector generation, V and T) in FP64 and run the
  * trailing updates (UNMQR/TSMQR/TTMQR and their LQ twins) on FP32 matrix
@@ -94,6 +103,9 @@ typedef struct {
     double watchdog_s;   /* persistent scheduler: seconds without progress before
                             BB_ETIMEOUT; 0 = 30 s */
     int    flags;        /* BB_FLAG_* */
+    int    switch_step;  /* BB_THREESTEP: > 0 forces the switch step s; 0 = from delta */
+    double delta;        /* BB_THREESTEP: switch ratio; 0 = 5 (Section 4.3.4 puts
+                            the switching point at 5 to 8) */
 } bb_opts;
 
 #define BB_FLAG_TIMING 1  /* record HIP events around the main kernel(s) */
@@ -118,7 +130,8 @@ typedef struct {
  * bb_plan_create -- build the task graph of one reduction (host work only: no
  * device memory and no device work; the host copy of the graph is
  * page-locked when a device is present).  Arguments: out plan (1), m (2),
- * n (3) with m >= n >= 1, nb (4) in {32, 64, 128, 256}, tree (5)
+ * n (3) >= 1 (m < n: the graph of A^T, see above), nb (4) in
+ * {32, 64, 128, 256}, tree (5)
  * BB_FLATTS..BB_AUTO, variant (6), prec (7) BB_F64*,
  * opts (8, may be NULL for defaults).  The plan is independent of the data and
  * of lda; it can be executed any number of times.
@@ -388,6 +401,20 @@ int bb_plan_auto_domains(const bb_plan* plan, int32_t* a, int64_t* nsteps);
  */
 double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int workgroups,
                         double gamma);
+
+/*
+ * bb_choose -- the (tree, variant) with the shortest estimated run time for
+ * an m x n matrix at tile size nb, among BiDiag, R-BiDiag and the three-step
+ * reduction (switch step from delta) with the Greedy and Auto trees
+ * (Sections 4.3.4 and 4.5 compare these by critical path; here the
+ * estimate is the list schedule of each task graph on opts->workgroups
+ * workers under the execution-cost model the device scheduler orders work
+ * with, which accounts for both the critical path and the total work).
+ * Host only.  Arguments: m (1), n (2), nb (3), opts (4, may be NULL),
+ * out tree (5), out variant (6), out estimate (7, may be NULL: the
+ * schedule length in cost-model units, for comparisons only).
+ */
+int bb_choose(int64_t m, int64_t n, int nb, const bb_opts* opts, int* tree, int* variant, double* estimate);
 
 /* Drop every plan the one-shot entry points cache (bidiag_band, bb_query,
  * bidiag_band_batched).  Plans in use by a running call are released when

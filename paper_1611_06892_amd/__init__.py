@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbidiag.so")
 
 TREES = {"flatts": 0, "flattt": 1, "greedy": 2, "auto": 3}
-VARIANTS = {"bidiag": 0, "rbidiag": 1, "qronly": 2}
+VARIANTS = {"bidiag": 0, "rbidiag": 1, "qronly": 2, "threestep": 3}
 PRECS = {"f64": 0, "f64_upd_f32": 2, "f64_upd_split32": 3}
 SCHEDS = {"persistent": 0, "levels": 1}
 KINDS = ["GEQRT", "TSQRT", "TTQRT", "UNMQR", "TSMQR", "TTMQR"]
@@ -37,7 +37,8 @@ class BidiagError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int), ("gamma", ctypes.c_double),
                 ("auto_a", ctypes.c_int), ("sched", ctypes.c_int),
-                ("watchdog_s", ctypes.c_double), ("flags", ctypes.c_int)]
+                ("watchdog_s", ctypes.c_double), ("flags", ctypes.c_int),
+                ("switch_step", ctypes.c_int), ("delta", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -59,7 +60,7 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
            "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear",
-           "bb_execute_noalloc"]
+           "bb_execute_noalloc", "bb_choose"]
 
 
 def lib():
@@ -140,6 +141,8 @@ def lib():
     L.bb_adjoint_workspace.restype = i32
     L.bb_adjoint_poll_error.argtypes = [P, vp, vp, ip]
     L.bb_adjoint_poll_error.restype = i32
+    L.bb_choose.argtypes = [i64, i64, i32, ctypes.POINTER(_Opts), ip, ip, ctypes.POINTER(ctypes.c_double)]
+    L.bb_choose.restype = i32
     L.bb_execute_noalloc.argtypes = [P, vp, i64, vp, ctypes.c_size_t, vp]
     L.bb_execute_noalloc.restype = i32
     L.bb_cache_clear.argtypes = []
@@ -161,6 +164,16 @@ def query(m, n, nb, tree="auto", variant="bidiag", prec="f64", **opts):
     return vt.value, ws.value
 
 
+def choose(m, n, nb, **opts):
+    """(tree, variant, estimate): the shortest estimated schedule among BiDiag,
+    R-BiDiag and the three-step reduction with the Greedy and Auto trees."""
+    o = make_opts(**opts)
+    tr, var, est = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().bb_choose(int(m), int(n), int(nb), ctypes.byref(o), ctypes.byref(tr), ctypes.byref(var),
+                           ctypes.byref(est)), "bb_choose")
+    return TREE_NAMES[tr.value], VARIANT_NAMES[var.value], est.value
+
+
 def cache_clear():
     """Drop the plans the one-shot entry points cache."""
     lib().bb_cache_clear()
@@ -176,9 +189,10 @@ def _check(rc: int, where: str):
 
 
 def make_opts(workgroups=0, gamma=0.0, auto_a=0, sched="persistent", watchdog_s=0.0,
-              timing=False, trace=False) -> _Opts:
+              timing=False, trace=False, switch_step=0, delta=0.0) -> _Opts:
     return _Opts(int(workgroups), float(gamma), int(auto_a), SCHEDS[sched], float(watchdog_s),
-                 (FLAG_TIMING if timing else 0) | (FLAG_TRACE if trace else 0))
+                 (FLAG_TIMING if timing else 0) | (FLAG_TRACE if trace else 0),
+                 int(switch_step), float(delta))
 
 
 def critical_path(p: int, q: int, tree="greedy", variant="bidiag", auto_a=0, workgroups=256,

@@ -1,9 +1,9 @@
 """Build libbidiag.so in-tree with hipcc for gfx950.
 
-The tile kernels are compiled once per (tile size, arithmetic) pair (nb = 32,
-64, 128, 256; FP64, FP32 and split-FP32 updates) and once for their
-size-independent part, from the same source, in parallel with the host
-sources.
+The tile kernels are compiled once per (tile size, kernel family) pair (nb =
+32, 64, 128, 256; reductions with FP64, FP32 or split-FP32 updates, and the
+applications of Q and P) and once for their size-independent part, from the
+same source, in parallel with the host sources.
 
 Usage: python -m paper_1611_06892_amd.build   (or build() from Python)
 """
@@ -35,12 +35,12 @@ def _jobs():
     """(object, command) for every translation unit."""
     hipcc = _hipcc()
     common = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-I", os.path.join(HERE, "..", "include")]
-    device = [hipcc, "-x", "hip", "--offload-arch=" + ARCH, "-munsafe-fp-atomics",
+    device = [hipcc, "-x", "hip", "--offload-arch=" + ARCH, "-munsafe-fp-atomics", "-Wno-unneeded-internal-declaration",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *common]
     jobs = []
     kern = os.path.join(CSRC, "kernels.hip")
     for nb in TILE_SIZES:
-        for prec in PRECS:
+        for prec in PRECS + (1,):       # 1: the application kernels
             obj = os.path.join(OBJDIR, "kernels_nb%d_p%d.o" % (nb, prec))
             jobs.append((obj, [*device, "-DBB_KERNELS_NB=%d" % nb, "-DBB_KERNELS_PREC=%d" % prec,
                                "-c", kern, "-o", obj]))

@@ -85,6 +85,12 @@ struct bb_plan {
     std::vector<int32_t> units_level;        // (task, part) pairs sorted by level
     std::vector<int32_t> level_off;          // units_level offsets per level
     double cp = 0.0, total = 0.0;
+    double makespan = 0.0;                   // length of the list schedule (cost-model units)
+    bool apply_graph = false;                // applies Q or P (bb_apply_q/p), no panels
+    // m < n (Section 3.6): the graph reduces A^T, whose tile (i, j) is tile
+    // (j, i) of A seen transposed; the device tasks swap the tile
+    // coordinates and flip the transpose flag, so A's storage is used as is.
+    bool transposed = false;
     // Host copy of the graph the device reads, uploaded into the workspace
     // by every execution: tasks, initial dependency counts, successors, the
     // unit order of the chosen schedule, batched descriptors' sources.
@@ -250,6 +256,8 @@ int build_schedule(bb_plan& P) {
         }
     }
 
+    P.makespan = now;
+
     // The persistent scheduler claims units in this simulated start order
     // (topological: a unit starts after its predecessors finished).
     P.units_prio = P.units_ticket;
@@ -318,7 +326,8 @@ int build_blob(bb_plan& P) {
     bbk::DevTask* dt = (bbk::DevTask*)(h + P.off_tasks);
     for (size_t t = 0; t < nt; ++t) {
         const bb::Task& s = P.g.tasks[t];
-        dt[t] = bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
+        dt[t] = P.transposed ? bbk::DevTask{s.kind, s.trans ^ 1, s.c1, s.r1, s.c2, s.r2, s.slot, s.mat}
+                             : bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
     }
     auto put32 = [&](size_t o, const std::vector<int32_t>& v) {
         if (!v.empty()) std::memcpy(h + o, v.data(), v.size() * 4);
@@ -352,6 +361,10 @@ int device_attr(hipDeviceAttribute_t attr, int fallback) {
         return fallback;
     return v;
 }
+
+// The kernel family a plan runs: its arithmetic for reductions, the
+// application kernels for the graphs that apply Q or P.
+int kernel_prec(const bb_plan& P) { return P.apply_graph ? bbk::PREC_APPLY : P.prec; }
 
 int plan_events(bb_plan& P) {
     std::call_once(P.ev_once, [&P] {
@@ -399,11 +412,11 @@ int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipSt
             const int cus = device_attr(hipDeviceAttributeMultiprocessorCount, P.opts.workgroups);
             int wg = std::min(P.opts.workgroups, cus);
             wg = std::max(1, std::min(wg, a.nunits));
-            if (bbk::launch_persistent(P.nb, P.prec, a, wg, s) != hipSuccess) return BB_EHIP;
+            if (bbk::launch_persistent(P.nb, kernel_prec(P), a, wg, s) != hipSuccess) return BB_EHIP;
         } else {
             for (size_t l = 0; l + 1 < P.level_off.size(); ++l) {
                 int32_t b = P.level_off[l], e = P.level_off[l + 1];
-                if (bbk::launch_level(P.nb, P.prec, a, b, e - b, s) != hipSuccess) return BB_EHIP;
+                if (bbk::launch_level(P.nb, kernel_prec(P), a, b, e - b, s) != hipSuccess) return BB_EHIP;
             }
         }
     }
@@ -446,9 +459,11 @@ int get_apply(bb_plan* P, int side, int transpose, int64_t ncols, bb_plan** out)
     Q->tree = P->tree;
     Q->variant = P->variant;
     Q->prec = BB_F64;
+    Q->apply_graph = true;
     Q->opts = P->opts;
     try {
-        bb::build_apply_graph(P->g, side, transpose, (int)jc, Q->g);
+        // For a transposed plan, Q of A is P of A^T and the other way round.
+        bb::build_apply_graph(P->g, P->transposed ? 1 - side : side, transpose, (int)jc, Q->g);
         int rc = finish_plan(*Q);
         if (rc != BB_OK) {
             delete Q;
@@ -471,6 +486,7 @@ bb_opts resolved_opts(const bb_opts* o) {
     }
     if (!(r.gamma > 0.0)) r.gamma = 2.0;
     if (!(r.watchdog_s > 0.0)) r.watchdog_s = 30.0;
+    if (!(r.delta > 0.0)) r.delta = 5.0;
     return r;
 }
 
@@ -543,7 +559,7 @@ std::vector<double> cache_key(int64_t m, int64_t n, int nb, int tree, int varian
                               const bb_opts& o) {
     return {(double)m, (double)n, (double)nb, (double)tree, (double)variant, (double)prec,
             (double)o.workgroups, o.gamma, (double)o.auto_a, (double)o.sched, o.watchdog_s,
-            (double)o.flags};
+            (double)o.flags, (double)o.switch_step, o.delta};
 }
 
 // Wait until no copy enqueued from a plan's host memory can still be in
@@ -579,18 +595,20 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
     if (n < 1) return -3;
     if (nb < 1) return -4;
     if (tree < BB_FLATTS || tree > BB_AUTO) return -5;
-    if (variant < BB_BIDIAG || variant > BB_QRONLY) return -6;
+    if (variant < BB_BIDIAG || variant > BB_THREESTEP) return -6;
     if (prec != BB_F64 && prec != BB_F64_UPD_F32 && prec != BB_F64_UPD_SPLIT32) return -7;
-    if (m < n) return BB_ENOTSUP;
     if (!bbk::nb_supported(nb)) return BB_ENOTSUP;
     bb_opts o = resolved_opts(opts);
     if (o.sched != BB_SCHED_PERSISTENT && o.sched != BB_SCHED_LEVELS) return -8;
     if (o.workgroups <= 0) o.workgroups = default_workgroups();
-    int64_t p = (m + nb - 1) / nb, q = (n + nb - 1) / nb;
+    // tile grid of the matrix the graph reduces: A, or A^T when m < n
+    const bool tr = m < n;
+    int64_t p = ((tr ? n : m) + nb - 1) / nb, q = ((tr ? m : n) + nb - 1) / nb;
     if (p > (1 << 20) || q > (1 << 16)) return BB_ENOTSUP;
     bb_plan* P = new (std::nothrow) bb_plan();
     if (!P) return BB_ENOMEM;
     P->m = m; P->n = n; P->nb = nb; P->tree = tree; P->variant = variant; P->prec = prec;
+    P->transposed = tr;
     P->opts = o;
     bb::PlanOptions po;
     po.tree = tree;
@@ -598,6 +616,8 @@ int bb_plan_create(bb_plan** plan, int64_t m, int64_t n, int nb, int tree, int v
     po.workgroups = o.workgroups;
     po.gamma = o.gamma;
     po.auto_a = o.auto_a;
+    po.switch_step = o.switch_step > 0 ? o.switch_step : -1;
+    po.delta = o.delta;
     try {
         std::string err = bb::build_graph((int)p, (int)q, po, P->g);
         if (!err.empty()) {
@@ -644,6 +664,52 @@ void bb_plan_destroy(bb_plan* P) {
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
     delete P;
+}
+
+int bb_choose(int64_t m, int64_t n, int nb, const bb_opts* opts, int* tree, int* variant, double* estimate) {
+    if (m < 1) return -1;
+    if (n < 1) return -2;
+    if (nb < 1) return -3;
+    if (!tree) return -5;
+    if (!variant) return -6;
+    if (!bbk::nb_supported(nb)) return BB_ENOTSUP;
+    bb_opts o = resolved_opts(opts);
+    if (o.workgroups <= 0) o.workgroups = default_workgroups();
+    const bool tr = m < n;
+    const int64_t p = ((tr ? n : m) + nb - 1) / nb, q = ((tr ? m : n) + nb - 1) / nb;
+    if (p > (1 << 20) || q > (1 << 16)) return BB_ENOTSUP;
+    double best = -1.0;
+    try {
+        for (int v : {BB_BIDIAG, BB_RBIDIAG, BB_THREESTEP}) {
+            if (v == BB_THREESTEP) {
+                const int s = bb::three_step_switch((int)p, (int)q, o.delta);
+                if (s == 0 || s == (int)q) continue;     // the same graph as R-BiDiag or BiDiag
+            }
+            for (int t : {BB_GREEDY, BB_AUTO}) {
+                bb_plan P;
+                P.m = m; P.n = n; P.nb = nb; P.tree = t; P.variant = v; P.prec = BB_F64; P.opts = o;
+                bb::PlanOptions po;
+                po.tree = t;
+                po.variant = v;
+                po.workgroups = o.workgroups;
+                po.gamma = o.gamma;
+                po.auto_a = o.auto_a;
+                po.switch_step = -1;
+                po.delta = o.delta;
+                if (!bb::build_graph((int)p, (int)q, po, P.g).empty()) return BB_EDAG;
+                if (build_schedule(P) != BB_OK) return BB_EDAG;
+                if (best < 0.0 || P.makespan < best) {
+                    best = P.makespan;
+                    *tree = t;
+                    *variant = v;
+                }
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return BB_ENOMEM;
+    }
+    if (estimate) *estimate = best;
+    return BB_OK;
 }
 
 void bb_cache_clear(void) {
@@ -859,6 +925,7 @@ int bidiag_band_adjoint(bb_plan* P, const void* B, int64_t ldb, const void* W, i
     if (!ws) return -10;
     if (P->variant == BB_QRONLY) return BB_ENOTSUP;
     if (P->nb > 128) return BB_ENOTSUP;     // the sweep's block solves cover nb <= 128
+    if (P->transposed) return BB_ENOTSUP;
     AdjLayout L;
     int rc = adjoint_layout(P, L);
     if (rc != BB_OK) return rc;
@@ -1114,7 +1181,7 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
             }
             if (!bbk::nb_supported(B->nb[i])) { delete B; return BB_ENOTSUP; }
             if (B->tree[i] < BB_FLATTS || B->tree[i] > BB_AUTO) { delete B; return -6; }
-            if (B->variant[i] < BB_BIDIAG || B->variant[i] > BB_QRONLY) { delete B; return -7; }
+            if (B->variant[i] < BB_BIDIAG || B->variant[i] > BB_THREESTEP) { delete B; return -7; }
             if ((B->m[i] + B->nb[i] - 1) / B->nb[i] > (1 << 20)) { delete B; return BB_ENOTSUP; }
         }
         B->rec_off.assign(count, 0);
@@ -1147,6 +1214,8 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
                 po.workgroups = o.workgroups;
                 po.gamma = o.gamma;
                 po.auto_a = o.auto_a;
+                po.switch_step = o.switch_step > 0 ? o.switch_step : -1;
+                po.delta = o.delta;
                 const int p = (int)((B->m[i] + tile - 1) / tile), q = (int)((B->n[i] + tile - 1) / tile);
                 bb::Graph gi;
                 if (!bb::build_graph(p, q, po, gi).empty()) { delete B; return BB_EDAG; }
@@ -1317,6 +1386,8 @@ int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, con
         key.push_back(o.sched);
         key.push_back((int64_t)(o.watchdog_s * 1e3));
         key.push_back(o.flags);
+        key.push_back(o.switch_step);
+        key.push_back((int64_t)(o.delta * 1e6));
         for (int64_t i = 0; i < count; ++i) {
             key.push_back(m[i]);
             key.push_back(n[i]);

@@ -1136,37 +1136,41 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
     if (active) store_slice_r4<CO, MT>(T2, c0, c2);
 }
 
-// PREC: 0 = FP64 updates, 2 = FP32-MFMA updates, 3 = split-FP32 updates.
+// PREC: 0 = FP64 updates, 2 = FP32-MFMA updates, 3 = split-FP32 updates
+// (reductions: panels and updates); PREC_APPLY = the applications of Q and
+// P from finished records (FP64 updates of both directions, no panels).
+// Reductions and applications are separate kernels, so that neither carries
+// the register demand of the other's code.
 template <int NB, bool CO, int PREC>
 __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, double* lds, Prev& prev, int* sch) {
     const DevTask tk = a.tasks[task];      // task is wave-uniform: scalar loads
-    switch (tk.kind) {
-    case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds, prev); break;
-    case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds, prev); break;
-    case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds, prev); break;
-    case K_UNMQR:
-        if (PREC == 0) update<NB, K_UNMQR, CO, false>(a, tk, part, lds, prev, sch);
-        else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
-        break;
-    case K_TSMQR:
-        if (PREC == 0) update<NB, K_TSMQR, CO, false>(a, tk, part, lds, prev, sch);
-        else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
-        break;
-    case K_TTMQR:
-        if (PREC == 0) update<NB, K_TTMQR, CO, false>(a, tk, part, lds, prev, sch);
-        else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
-        break;
-    // Applications of Q itself (records of a finished reduction, FP64 only;
-    // the host builds them for PREC 0 alone).
-    case K_UNMQR + K_HQ:
-        if (PREC == 0) update<NB, K_UNMQR, CO, true>(a, tk, part, lds, prev, sch);
-        break;
-    case K_TSMQR + K_HQ:
-        if (PREC == 0) update<NB, K_TSMQR, CO, true>(a, tk, part, lds, prev, sch);
-        break;
-    default:
-        if (PREC == 0) update<NB, K_TTMQR, CO, true>(a, tk, part, lds, prev, sch);
-        break;
+    if constexpr (PREC == PREC_APPLY) {
+        switch (tk.kind) {
+        case K_UNMQR: update<NB, K_UNMQR, CO, false>(a, tk, part, lds, prev, sch); break;
+        case K_TSMQR: update<NB, K_TSMQR, CO, false>(a, tk, part, lds, prev, sch); break;
+        case K_TTMQR: update<NB, K_TTMQR, CO, false>(a, tk, part, lds, prev, sch); break;
+        case K_UNMQR + K_HQ: update<NB, K_UNMQR, CO, true>(a, tk, part, lds, prev, sch); break;
+        case K_TSMQR + K_HQ: update<NB, K_TSMQR, CO, true>(a, tk, part, lds, prev, sch); break;
+        default: update<NB, K_TTMQR, CO, true>(a, tk, part, lds, prev, sch); break;
+        }
+    } else {
+        switch (tk.kind) {
+        case K_GEQRT: panel<NB, K_GEQRT, CO>(a, tk, lds, prev); break;
+        case K_TSQRT: panel<NB, K_TSQRT, CO>(a, tk, lds, prev); break;
+        case K_TTQRT: panel<NB, K_TTQRT, CO>(a, tk, lds, prev); break;
+        case K_UNMQR:
+            if (PREC == 0) update<NB, K_UNMQR, CO, false>(a, tk, part, lds, prev, sch);
+            else update32<NB, K_UNMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
+            break;
+        case K_TSMQR:
+            if (PREC == 0) update<NB, K_TSMQR, CO, false>(a, tk, part, lds, prev, sch);
+            else update32<NB, K_TSMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
+            break;
+        default:
+            if (PREC == 0) update<NB, K_TTMQR, CO, false>(a, tk, part, lds, prev, sch);
+            else update32<NB, K_TTMQR, CO, PREC == 3>(a, tk, part, lds, prev, sch);
+            break;
+        }
     }
     retire(a, prev);               // a kind that ran nothing
 }
@@ -1346,6 +1350,10 @@ template hipError_t launch_persistent_np<BB_KERNELS_NB, BB_KERNELS_PREC>(const K
     case 256 * 4 + 0: return F<256, 0>(__VA_ARGS__);                               \
     case 256 * 4 + 2: return F<256, 2>(__VA_ARGS__);                               \
     case 256 * 4 + 3: return F<256, 3>(__VA_ARGS__);                               \
+    case 32 * 4 + PREC_APPLY: return F<32, PREC_APPLY>(__VA_ARGS__);               \
+    case 64 * 4 + PREC_APPLY: return F<64, PREC_APPLY>(__VA_ARGS__);               \
+    case 128 * 4 + PREC_APPLY: return F<128, PREC_APPLY>(__VA_ARGS__);             \
+    case 256 * 4 + PREC_APPLY: return F<256, PREC_APPLY>(__VA_ARGS__);             \
     default: return hipErrorInvalidValue;                                          \
     }
 

@@ -55,7 +55,9 @@ hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks
 // arrays; gidx, dims: the plan's device copy).
 hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
                              double* const* A, const int64_t* lda, hipStream_t s);
-// prec: 0 = FP64, 2 = FP32-MFMA updates, 3 = split-FP32 updates (bidiag.h's BB_F64*).
+// prec: 0 = FP64, 2 = FP32-MFMA updates, 3 = split-FP32 updates (bidiag.h's
+// BB_F64*) for reductions; PREC_APPLY for the application graphs of Q and P.
+constexpr int PREC_APPLY = 1;
 hipError_t launch_level(int nb, int prec, const KArgs& a, int32_t unit_base, int32_t count, hipStream_t s);
 hipError_t launch_persistent(int nb, int prec, const KArgs& a, int32_t workgroups, hipStream_t s);
 // The same for one (tile size, arithmetic) pair (each pair's kernels are

@@ -154,67 +154,88 @@ struct Builder {
         ensure_tri(s, 0);
     }
 
-    // QR(p,q) with the Greedy tree over all columns at once (used by
-    // R-BiDiag).  Synchronous rounds: in column j the rows already zeroed in
-    // column j-1 but not yet in column j are candidates; the bottom half of
-    // them is eliminated (TT) by the rows just above.
-    void greedy_qr(int pend) {
+    // QR of tile rows j0..pend-1, tile columns j0..q-1 with the Greedy tree
+    // over all columns at once (used by R-BiDiag, j0 = 0, and by the
+    // three-step reduction).  Synchronous rounds: in column j the rows
+    // already zeroed in column j-1 but not yet in column j are candidates;
+    // the bottom half of them is eliminated (TT) by the rows just above.
+    void greedy_qr(int pend, int j0) {
         std::vector<StepState> cols;
-        for (int j = 0; j < q; ++j) cols.push_back(make_step(0, j, j, pend, j + 1, q));
-        for (int j = 0; j < q; ++j) g.auto_a_used.push_back(0);
-        std::vector<int> nz(q, 0);
+        for (int j = j0; j < q; ++j) cols.push_back(make_step(0, j, j, pend, j + 1, q));
+        for (int j = j0; j < q; ++j) g.auto_a_used.push_back(0);
+        const int nc = q - j0;
+        std::vector<int> nz(nc, 0);
         for (;;) {
             std::vector<int> nzn = nz;
             bool any = false;
-            for (int j = 0; j < q; ++j) {
-                int top = (j == 0) ? 0 : pend - nz[j - 1];
+            for (int jj = 0; jj < nc; ++jj) {
+                const int j = j0 + jj;
+                int top = (jj == 0) ? j0 : pend - nz[jj - 1];
                 top = std::max(top, j);
-                int bottom = pend - nz[j];
+                int bottom = pend - nz[jj];
                 int z = bottom - top;
                 int e = z / 2;
                 for (int t = 0; t < e; ++t) {
                     int i = bottom - 1 - t;
-                    eliminate(cols[j], Elim{i - j, i - e - j, 1});
+                    eliminate(cols[jj], Elim{i - j, i - e - j, 1});
                 }
-                nzn[j] += e;
+                nzn[jj] += e;
                 if (e > 0) any = true;
             }
             nz = nzn;
             if (!any) break;
         }
-        for (int j = 0; j < q; ++j) ensure_tri(cols[j], 0);
+        for (int jj = 0; jj < nc; ++jj) ensure_tri(cols[jj], 0);
+    }
+
+    // R-BiDiag on the trailing tiles (s.., s..): QR of rows s..p-1, columns
+    // s..q-1, then the band reduction of the top (q-s) x (q-s) tiles.
+    void rbidiag_from(int s, bool qr_only) {
+        if (g.opt.tree == GREEDY) {
+            greedy_qr(p, s);
+        } else {
+            for (int k = s; k < q; ++k) run_step(0, k, k, p, k + 1, q);
+        }
+        if (qr_only) return;
+        g.phase2_start = (int32_t)g.tasks.size();
+        for (int k = s; k < q; ++k) {
+            if (k > s) run_step(0, k, k, q, k + 1, q);       // QR(k) on the top tiles
+            if (k + 1 < q) run_step(1, k, k + 1, q, k + 1, q);  // LQ(k)
+        }
     }
 };
 
 }  // namespace
 
+int three_step_switch(int p, int q, double delta) {
+    for (int k = 0; k < q; ++k)
+        if ((double)(p - k) >= delta * (double)(q - k)) return k;
+    return q;
+}
+
 std::string build_graph(int p, int q, const PlanOptions& opt, Graph& g) {
     if (q < 1 || p < q) return "tile grid must satisfy p >= q >= 1";
     if (opt.tree < FLATTS || opt.tree > AUTO) return "unknown tree";
-    if (opt.variant < BIDIAG || opt.variant > QRONLY) return "unknown variant";
+    if (opt.variant < BIDIAG || opt.variant > THREESTEP) return "unknown variant";
     g = Graph();
     g.p = p;
     g.q = q;
     g.opt = opt;
     Builder b(g, p, q);
-    if (opt.variant == BIDIAG) {
-        for (int k = 0; k < q; ++k) {
-            b.run_step(0, k, k, p, k + 1, q);                 // QR(k)
-            if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, p);  // LQ(k)
-        }
-    } else {
-        if (opt.tree == GREEDY) {
-            b.greedy_qr(p);
-        } else {
-            for (int k = 0; k < q; ++k) b.run_step(0, k, k, p, k + 1, q);
-        }
-        if (opt.variant == QRONLY) return std::string();
-        g.phase2_start = (int32_t)g.tasks.size();
-        for (int k = 0; k < q; ++k) {
-            if (k > 0) b.run_step(0, k, k, q, k + 1, q);       // QR(k) on the top q x q
-            if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, q);  // LQ(k)
-        }
+    // BiDiag steps QR(k); LQ(k) for k < s, then R-BiDiag on what is left
+    // (Sections 3.4, 3.5 and 4.5).
+    int s = 0;
+    switch (opt.variant) {
+    case BIDIAG: s = q; break;
+    case RBIDIAG: case QRONLY: s = 0; break;
+    default: s = opt.switch_step >= 0 ? std::min(opt.switch_step, q) : three_step_switch(p, q, opt.delta); break;
     }
+    g.switch_step = s;
+    for (int k = 0; k < s; ++k) {
+        b.run_step(0, k, k, p, k + 1, q);                     // QR(k)
+        if (k + 1 < q) b.run_step(1, k, k + 1, q, k + 1, p);  // LQ(k)
+    }
+    if (s < q) b.rbidiag_from(s, opt.variant == QRONLY);
     return std::string();
 }
 

@@ -29,7 +29,10 @@ enum : int { APPLY_H = 3, NKINDS = 9 };
 enum Tree : int { FLATTS = 0, FLATTT = 1, GREEDY = 2, AUTO = 3 };
 // QRONLY is the tiled QR factorization QR(p,q) of Algorithm 1 alone (the first
 // phase of R-BiDiag); it exists for the critical-path formulas of Section 4.3.
-enum Variant : int { BIDIAG = 0, RBIDIAG = 1, QRONLY = 2 };
+// THREESTEP is the three-step reduction of Section 4.5: BiDiag steps
+// QR(k); LQ(k) for k < s, then R-BiDiag on the trailing (p-s) x (q-s) tiles
+// (s = 0 is R-BiDiag, s = q is BiDiag).
+enum Variant : int { BIDIAG = 0, RBIDIAG = 1, QRONLY = 2, THREESTEP = 3 };
 
 inline bool is_panel(int k) { return k <= TTQRT; }
 
@@ -53,7 +56,14 @@ struct PlanOptions {
     int workgroups = 256;   // concurrent workers assumed by Auto (nb_cores in Section 5)
     double gamma = 2.0;     // Auto's parallelism factor (Section 5 uses 2)
     int auto_a = 0;         // > 0 forces the FlatTS domain size of Auto
+    int switch_step = -1;   // THREESTEP: the step s; < 0 chooses it by delta
+    double delta = 5.0;     // THREESTEP: switch once the trailing tiles have p - k >= delta (q - k)
 };
+
+// THREESTEP's switch step for a p x q tile matrix: the first k with
+// p - k >= delta (q - k) (the trailing matrix is then tall enough for
+// R-BiDiag to have the shorter critical path, Sections 4.3.4 and 4.5), else q.
+int three_step_switch(int p, int q, double delta);
 
 struct Graph {
     int p = 0, q = 0;
@@ -64,6 +74,7 @@ struct Graph {
     int32_t nsteps = 0;
     std::vector<int32_t> auto_a_used;        // per step (Auto), for inspection
     int32_t phase2_start = -1;               // R-BiDiag: first task of the band reduction of R
+    int32_t switch_step = -1;                // THREESTEP: the step s used
 };
 
 // Build the task graph.  Returns an empty string on success, else a message.

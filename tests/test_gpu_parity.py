@@ -124,3 +124,17 @@ def test_tall_graded_full_size(bb, variant, tree):
     sB = np.linalg.svd(Bg[:n], compute_uv=False)
     err = np.max(np.abs(sB - s))
     assert err <= 50 * n * EPS * np.linalg.norm(A), err
+
+
+@pytest.mark.parametrize("m,n,nb,tree,opts", [
+    (2048, 512, 64, "greedy", {}),                  # 32 x 8 tiles: switches at step 2
+    (2048, 512, 64, "auto", {"switch_step": 5}),
+    (1100, 300, 32, "flatts", {"delta": 3.0}),      # ragged
+    (1500, 700, 128, "flattt", {"switch_step": 2}),
+])
+def test_three_step_matches_oracle(bb, m, n, nb, tree, opts):
+    """The three-step reduction (Section 4.5) reaches the same band form."""
+    A = workloads.gaussian(m, n, seed=4000 + m + n)
+    print("case threestep", m, n, nb, tree, opts, flush=True)
+    Bg, _ = run_gpu(bb, A, nb, tree, "threestep", sched="persistent", **opts)
+    check_against_oracle(A, Bg, nb)

@@ -36,7 +36,6 @@ def test_argument_errors():
     L = bb.lib()
     h = ctypes.c_void_p()
     opts = bb.make_opts()
-    assert L.bb_plan_create(ctypes.byref(h), 100, 200, 64, 0, 0, 0, ctypes.byref(opts)) == 1  # m < n
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 48, 0, 0, 0, ctypes.byref(opts)) == 1   # nb
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 9, 0, 0, ctypes.byref(opts)) == -5  # tree
     assert L.bb_plan_create(ctypes.byref(h), 100, 50, 64, 0, 7, 0, ctypes.byref(opts)) == -6  # variant
@@ -350,3 +349,63 @@ def test_nb256_plan_splits_updates_in_halves():
         h = ctypes.c_void_p()
         opts = bb.make_opts()
         assert bb.lib().bb_plan_create(ctypes.byref(h), 2000, 1000, nb, 2, 0, 0, ctypes.byref(opts)) == 1
+
+
+def test_wide_matrix_plans_the_transpose():
+    """m < n (Section 3.6): the graph is the one of A^T (p = ceil(n/nb) tile
+    rows, q = ceil(m/nb) tile columns), the same graph as an n x m plan."""
+    for (m, n, nb) in [(100, 200, 64), (300, 1000, 128), (500, 501, 32)]:
+        wide = bb.Plan(m, n, nb, "greedy", "rbidiag")
+        tall = bb.Plan(n, m, nb, "greedy", "rbidiag")
+        sw, st = wide.stats(), tall.stats()
+        assert (sw["p"], sw["q"]) == (-(-n // nb), -(-m // nb))
+        assert sw == st
+        assert wide.workspace() == tall.workspace()
+        tw, _, _ = wide.export()
+        tt, _, _ = tall.export()
+        np.testing.assert_array_equal(tw, tt)
+
+
+def test_three_step_switch_rule_and_graphs():
+    """Section 4.5's three-step reduction: BiDiag steps until the trailing
+    tile matrix is tall enough (p - k >= delta (q - k), Section 4.3.4's
+    switching point), then R-BiDiag on it.  With the switch at q it is
+    BiDiag's graph; forced at step s it is a valid graph between the two."""
+    nb = 64
+    # 64 x 16 tiles, delta = 5: 64 - k >= 5 (16 - k) first at k = 4
+    # (FlatTS, where R-BiDiag's path is much shorter on tall inputs, puts the
+    # three-step path between the two)
+    p3 = bb.Plan(64 * nb, 16 * nb, nb, "flatts", "threestep")
+    pb = bb.Plan(64 * nb, 16 * nb, nb, "flatts", "bidiag")
+    pr = bb.Plan(64 * nb, 16 * nb, nb, "flatts", "rbidiag")
+    c3, cb, cr = (x.stats()["critical_path"] for x in (p3, pb, pr))
+    assert cr < c3 < cb, (cr, c3, cb)
+    # a square matrix never switches: the three-step graph is BiDiag's
+    sq3 = bb.Plan(8 * nb, 8 * nb, nb, "auto", "threestep")
+    sqb = bb.Plan(8 * nb, 8 * nb, nb, "auto", "bidiag")
+    np.testing.assert_array_equal(sq3.export()[0], sqb.export()[0])
+    # forced switch steps give race-free graphs with the same number of panels
+    # per column step as R-BiDiag after the switch
+    for s in (1, 3, 7):
+        f = bb.Plan(20 * nb, 8 * nb, nb, "flatts", "threestep", switch_step=s)
+        t, off, idx = f.export()
+        assert bb.graph_check(20, 8, t, off, idx) == 0
+    # the switching rule itself (delta = 5, and a larger delta switches later)
+    for (p, q, delta, s) in [(64, 16, 5.0, 4), (16, 16, 5.0, 16), (80, 16, 5.0, 0), (64, 16, 8.0, 10)]:
+        f = bb.Plan(p * nb, q * nb, nb, "greedy", "threestep", delta=delta)
+        g = bb.Plan(p * nb, q * nb, nb, "greedy", "threestep", switch_step=s) if 0 < s < q else \
+            bb.Plan(p * nb, q * nb, nb, "greedy", "rbidiag" if s == 0 else "bidiag")
+        np.testing.assert_array_equal(f.export()[0], g.export()[0])
+
+
+def test_choose_picks_by_shape():
+    """The chooser's schedule estimate prefers R-BiDiag for very tall
+    matrices and BiDiag for square ones (Section 6.2's observation that
+    R-BiDiag wins for tall-and-skinny inputs and BiDiag for square ones)."""
+    t, v, e = bb.choose(32768, 2048, 128)
+    assert v in ("rbidiag", "threestep") and e > 0
+    t, v, e = bb.choose(4096, 4096, 128)
+    assert v == "bidiag"
+    t2, v2, e2 = bb.choose(4096, 2 * 4096, 128)     # wide: the transpose's choice
+    t3, v3, e3 = bb.choose(2 * 4096, 4096, 128)
+    assert (t2, v2, e2) == (t3, v3, e3)
