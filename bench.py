@@ -1,42 +1,51 @@
 #!/usr/bin/env python3
 """Band-bidiagonalization throughput on one MI355X.
 
-Workload: the tall graded matrix, 32768 x 2048, A = U diag(s) V^T with s
-geometric from 1 to 1e-8 (seeded), tile nb = 128, reduced to band form by
-R-BiDiag (QR(p,q) then the band reduction of R, Section 3.5) with the Greedy
-tree by default.  One step = one full reduction of a fresh copy of A already
-resident in HBM (the copy is inside the timed region).  GFLOP/s uses the
-paper's operation count 4 n^2 (m - n/3) for both BiDiag and R-BiDiag
-(Section 6.2).  Also reported: BiDiag / R-BiDiag x Greedy / Auto on the same
-input, the roofline of the persistent kernel (HIP events on the launch
-stream), and the FP64 oracle timed on host cores on a bounded sample.
+Headline workload: the square graded matrix, 16384 x 16384, A = U diag(s) V^T
+with s geometric from 1 to 1e-6 (seeded), tile nb = 256, reduced to band form
+by BiDiag (Section 3.4) with the Auto tree, FP64.  One step = one full
+reduction of a fresh copy of A already resident in HBM (the copy is inside the
+timed region).  GFLOP/s uses the paper's operation count 4 n^2 (m - n/3)
+(Section 6.2).  The line also carries the roofline of the persistent kernel
+(HIP events on its launch stream), the FP64 oracle timed on host cores on a
+bounded sample of the same recipe (all cores and one thread), and extra keys
+for the other workloads: the tall graded 32768 x 2048 reduction, the batch of
+4096 matrices, the adjoint of the 8192 x 1024 reduction, the same square at
+nb = 128 and its FP32-update form.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
 METRIC = "band-bidiag GFLOP/s (4n²(m−n/3)/t), % MFMA peak, mixed/batched vs FP64 at err"
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+HERE = os.path.dirname(os.path.abspath(__file__))
+DTYPES = {"f64": "f64", "f64_upd_f32": "f64 panels, f32 updates",
+          "f64_upd_split32": "f64 panels, split-f32 updates"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_plan(bb, torch, plan, S0, m, steps, warmup):
+def time_plan(bb, torch, plan, S0, m, steps, warmup, label=""):
+    """Warmup, then `steps` timed reductions of fresh copies of S0.
+    Returns (wall ms per step, kernel ms per step list, the reduced copy)."""
     vt, ws = plan.alloc()
     S = torch.empty_like(S0)
     for w in range(warmup):
         S.copy_(S0)
         plan.execute(S, m, vt, ws)
-        log("  warmup %d: %.2f ms" % (w, plan.last_kernel_ms()))
+        log("  %s warmup %d: %.2f ms" % (label, w, plan.last_kernel_ms()))
     st = bb.poll_error(ws)
     if st != 0:
         raise RuntimeError("device scheduler error %d" % st)
@@ -47,96 +56,191 @@ def time_plan(bb, torch, plan, S0, m, steps, warmup):
         S.copy_(S0)
         plan.execute(S, m, vt, ws)
         kms.append(plan.last_kernel_ms())
-        log("  step %d: %.2f ms" % (k, kms[-1]))
+        log("  %s step %d: %.2f ms" % (label, k, kms[-1]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = bb.poll_error(ws)
     if st != 0:
         raise RuntimeError("device scheduler error %d" % st)
-    return (t1 - t0) * 1e3 / steps, kms, S
+    return (t1 - t0) * 1e3 / steps, kms, S, vt
 
 
-def measured_traffic(args, m, n, nb):
+def measured_traffic(workload, m, n, nb, variant, tree, prec):
     """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), for
-    the configuration it was measured on and only while the kernel source is
-    the one measured; else None."""
-    import hashlib
-    if (args.workload, m, n, nb, args.variant, args.tree, args.prec, args.sched) != \
-            ("tall_graded", 32768, 2048, 128, "rbidiag", "greedy", "f64", "persistent"):
+    summary of this configuration (FETCH_SIZE + WRITE_SIZE, calibrated on a
+    copy of known size), only while the kernel source is the one measured;
+    else None."""
+    name = "persistent_kernel_%s_%dx%d_nb%d_%s_%s.md" % (workload, m, n, nb, variant, tree)
+    if prec != "f64":
         return None
-    here = os.path.dirname(os.path.abspath(__file__))
-    summary = os.path.join(here, "profiles",
-                           "persistent_kernel_tall_graded_32768x2048_nb128_rbidiag_greedy.md")
-    src = os.path.join(here, "paper_1611_06892_amd", "csrc", "kernels.hip")
+    summary = os.path.join(HERE, "profiles", name)
+    src = os.path.join(HERE, "paper_1611_06892_amd", "csrc", "kernels.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(summary).read().splitlines()
                       if line.startswith(("traffic_bytes: ", "kernel_source_sha256_prefix: ")))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if fields.get("kernel_source_sha256_prefix") != sha:
+    if fields.get("kernel_source_sha256_prefix") != sha or "traffic_bytes" not in fields:
         return None
     return float(fields["traffic_bytes"])
 
 
-def cpu_baseline(workloads):
-    """The FP64 oracle on a bounded sample of the same workload."""
+ORACLE_SNIPPET = r"""
+import sys, time, json
+sys.path.insert(0, %r)
+import oracle, workloads
+m, n, nb, seeds, smin = %d, %d, %d, (%d, %d), %r
+A, _ = workloads.graded(m, n, seeds[0], seeds[1], smin)
+t0 = time.perf_counter()
+oracle.band_reduce(A, nb)
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "threads": oracle.num_threads(),
+                  "gflops": workloads.flops_bidiag(m, n) / dt / 1e9}))
+"""
+
+
+def oracle_rate(m, n, nb, seeds, smin, threads=None):
+    """The oracle (unblocked FP64 BiDiag) on one graded m x n matrix, in a
+    child process so that the OpenMP thread count can be set."""
+    env = dict(os.environ)
+    if threads is not None:
+        env["OMP_NUM_THREADS"] = str(threads)
+    code = ORACLE_SNIPPET % (HERE, m, n, nb, seeds[0], seeds[1], smin)
+    out = subprocess.check_output([sys.executable, "-c", code], env=env)
+    return json.loads(out.decode().strip().splitlines()[-1])
+
+
+def cpu_baseline_square():
+    """The oracle on bounded samples of the square graded recipe (nb = 256):
+    2048 x 2048 on all host cores, 1024 x 1024 on one thread."""
     import oracle
-    m, n, nb = 4096, 2048, 128
-    A, _ = workloads.graded(m, n, 1, 2, 1e-8)
-    t0 = time.perf_counter()
-    oracle.band_reduce(A, nb)
-    dt = time.perf_counter() - t0
-    return {"value": round(workloads.flops_bidiag(m, n) / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "4096 x 2048 graded matrix (same recipe, seeds 1/2), nb = 128, unblocked "
-                      "FP64 BiDiag, %.1f s" % dt}
+    oracle.build()
+    allc = oracle_rate(2048, 2048, 256, (3, 4), 1e-6)
+    one = oracle_rate(1024, 1024, 256, (3, 4), 1e-6, threads=1)
+    return {"value": round(allc["gflops"], 3), "unit": "GFLOP/s", "cores": allc["threads"],
+            "kind": "oracle",
+            "sample": "2048 x 2048 graded matrix of the same recipe (seeds 3/4, s 1..1e-6), nb = 256, "
+                      "unblocked FP64 BiDiag, %.1f s on %d threads" % (allc["seconds"], allc["threads"]),
+            "single_thread": {"value": round(one["gflops"], 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": "1024 x 1024 of the same recipe, nb = 256, %.1f s"
+                                        % one["seconds"]}}
 
 
-def bench_batch(args, bb, torch, np, workloads):
+def graded_input(bb, torch, np, workloads, m, n, seeds, smin):
+    if m * n <= 2 ** 27:
+        A, s = workloads.graded(m, n, *seeds, smin)
+        Ad = torch.from_numpy(A).cuda()
+    else:
+        Ad, s = workloads.graded_device(m, n, *seeds, smin)
+    return Ad, s
+
+
+def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, steps=None,
+                 warmup=None, probes=True, label="square"):
+    """The graded m x n square workload (default 16384^2): reduction timing,
+    band check, ||B||_F against ||s||, probe vectors through Q and P."""
+    cfg = workloads.CONFIGS["square_graded"]
+    m, n = args.m or cfg["m"], args.n or cfg["n"]
+    nb = nb or args.nb or cfg["nb"]
+    tree = tree or args.tree
+    prec = prec or args.prec
+    variant = args.variant
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    log("generating %d x %d graded input" % (m, n))
+    Ad, s = graded_input(bb, torch, np, workloads, m, n, cfg["seeds"], cfg["smin"])
+    nA = float(torch.linalg.norm(Ad))
+    S0 = bb.to_colmajor(Ad)
+    plan = bb.Plan(m, n, nb, tree, variant, prec=prec, sched=args.sched, timing=True,
+                   watchdog_s=60.0)
+    log("timing %s %s/%s nb=%d %s: %d warmup + %d steps" % (label, variant, tree, nb, prec, warmup, steps))
+    ms_step, kms, S, vt = time_plan(bb, torch, plan, S0, m, steps, warmup, label)
+    B = S.t()
+    i = torch.arange(m, device=B.device)[:, None]
+    j = torch.arange(n, device=B.device)[None, :]
+    band_ok = bool(torch.all(B[(j < i) | (j > i + nb)] == 0.0).item())
+    fro = abs(float(torch.linalg.norm(B)) - float(np.linalg.norm(s))) / float(np.linalg.norm(s))
+    probe = None
+    if probes:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(11)
+        X = torch.randn(n, 8, generator=gen, device="cuda", dtype=torch.float64)
+        Y1 = Ad @ X
+        Xs = X.t().contiguous()
+        plan.apply_p(Xs, n, 8, vt, transpose=True)
+        Zs = (B @ Xs.t()).t().contiguous()
+        plan.apply_q(Zs, m, 8, vt)
+        torch.cuda.synchronize()
+        probe = float(torch.linalg.norm(Y1 - Zs.t())) / (nA * float(torch.linalg.norm(X)))
+    del Ad, S0, S, B
+    kern_ms = float(np.mean(kms))
+    flops = workloads.flops_bidiag(m, n)
+    algo = workloads.flops_rbidiag_actual(m, n) if variant == "rbidiag" else flops
+    peak = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
+    achieved = algo / (kern_ms * 1e-3) / 1e12
+    return {
+        "m": m, "n": n, "nb": nb, "variant": variant, "tree": tree, "prec": prec,
+        "ms_per_step": ms_step, "kernel_ms": kern_ms, "gflops": flops / (ms_step * 1e-3) / 1e9,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic("square_graded", m, n, nb, variant, tree, prec),
+                     "kernel": "persistent_kernel<%d, %d>" % (nb, bb.PRECS[prec]),
+                     "kernel_ms": round(kern_ms, 3), "algorithmic_flops": algo},
+        "check": {"band_exact": band_ok, "fro_norm_rel_err": fro, "probe_rel_err": probe,
+                  "tol": 50 * n * np.finfo(np.float64).eps},
+    }
+
+
+def bench_tall(args, bb, torch, np, workloads, steps=5, warmup=2, variant="rbidiag", tree="greedy"):
+    """32768 x 2048 graded (s 1 .. 1e-8), nb = 128."""
+    cfg = workloads.CONFIGS["tall_graded"]
+    m, n, nb = cfg["m"], cfg["n"], cfg["nb"]
+    log("generating %d x %d graded input" % (m, n))
+    Ad, s = graded_input(bb, torch, np, workloads, m, n, cfg["seeds"], cfg["smin"])
+    S0 = bb.to_colmajor(Ad)
+    del Ad
+    plan = bb.Plan(m, n, nb, tree, variant, timing=True)
+    ms_step, kms, S, _ = time_plan(bb, torch, plan, S0, m, steps, warmup, "tall")
+    sB = np.linalg.svd(S.t()[:n].cpu().numpy(), compute_uv=False)
+    kern_ms = float(np.mean(kms))
+    flops = workloads.flops_bidiag(m, n)
+    algo = workloads.flops_rbidiag_actual(m, n) if variant == "rbidiag" else flops
+    return {"workload": "tall_graded %dx%d nb=%d %s %s" % (m, n, nb, variant, tree),
+            "gflops": round(flops / (ms_step * 1e-3) / 1e9, 2), "ms_per_step": round(ms_step, 3),
+            "kernel_ms": round(kern_ms, 3),
+            "frac_fp64_peak": round(algo / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "max_abs_sigma_err": float(np.max(np.abs(sB - s)))}
+
+
+def bench_batch(args, bb, torch, np, workloads, steps=3, warmup=1, prec="f64"):
     """4096 matrices, m ~ U{64..1024}, n ~ U{32..m}, N(0,1) (seed 5), each with
-    the tuned (nb, tree, variant) of its size class; one step = all of them,
-    from fresh copies already in HBM."""
+    the tuned (nb, tree, variant) of its size class."""
     cfg = workloads.CONFIGS["batch"]
     log("generating the batch")
     mats = workloads.batch_shapes(cfg["count"], cfg["seed"], cfg["mlo"], cfg["mhi"], cfg["nlo"])
     shapes = [A.shape for A in mats]
-    plan = bb.BatchPlan(shapes, prec=args.prec, timing=True)
+    plan = bb.BatchPlan(shapes, prec=prec, timing=True)
     buf, ptrs, ldas, offs = bb.pack_batch(mats)
     orig = buf.clone()
     vt, ws = plan.alloc()
-    log("batch: %d matrices, records %.1f GB" % (len(mats), vt.numel() / 1e9))
-    for w in range(args.warmup):
+    for w in range(warmup):
         buf.copy_(orig)
         plan.execute(ptrs, ldas, vt, ws)
-        log("  warmup %d: %.2f ms" % (w, plan.last_kernel_ms()))
+        log("  batch warmup %d: %.2f ms" % (w, plan.last_kernel_ms()))
     torch.cuda.synchronize()
     kms = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         buf.copy_(orig)
         plan.execute(ptrs, ldas, vt, ws)
         kms.append(plan.last_kernel_ms())
-        log("  step %d: %.2f ms" % (k, kms[-1]))
     torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    st = plan.poll_error(ws)
-    if st != 0:
-        raise RuntimeError("device scheduler error %d" % st)
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    if plan.poll_error(ws) != 0:
+        raise RuntimeError("device scheduler error in the batch")
     flops = sum(workloads.flops_bidiag(m, n) for m, n in shapes)
-    actual, classes = 0.0, {}
-    for i, (m, n) in enumerate(shapes):
-        inf = plan.info(i)
-        actual += (workloads.flops_rbidiag_actual(m, n) if inf["variant"] == "rbidiag"
-                   else workloads.flops_bidiag(m, n))
-        key = "nb%d/%s/%s" % (inf["nb"], inf["tree"], inf["variant"])
-        classes[key] = classes.get(key, 0) + 1
-    # correctness outside the timed region: band structure of every matrix,
-    # orthogonal invariance of the Frobenius norm, and the singular values of
-    # a sample against numpy's SVD of A
-    log("checking")
-    band_ok, fro_err, sig_err = True, 0.0, 0.0
+    band_ok, fro_err = True, 0.0
     for i, A in enumerate(mats):
         B = bb.unpack(buf, offs, shapes, i).cpu().numpy()
         nb = plan.info(i)["nb"]
@@ -145,133 +249,46 @@ def bench_batch(args, bb, torch, np, workloads):
         band_ok &= bool(np.all(B[(jj < ii) | (jj > ii + nb)] == 0.0))
         nA = np.linalg.norm(A)
         fro_err = max(fro_err, abs(np.linalg.norm(B) - nA) / nA)
-        if i % 256 == 0:
-            sa = np.linalg.svd(A, compute_uv=False)
-            sb = np.linalg.svd(B, compute_uv=False)
-            sig_err = max(sig_err, float(np.max(np.abs(sa - sb)) / nA))
-    kern_ms = float(np.mean(kms))
-    peak = FP64_PEAK_TFLOPS if args.prec == "f64" else FP32_PEAK_TFLOPS
-    achieved = actual / (kern_ms * 1e-3) / 1e12
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.perf_counter()
-        done = 0.0
-        for i, A in enumerate(mats[:64]):
-            oracle.band_reduce(A, plan.info(i)["nb"])
-            done += workloads.flops_bidiag(*A.shape)
-            if time.perf_counter() - t0 > 15.0:
-                break
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(done / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": "the first matrices of the batch until 15 s, "
-               "unblocked FP64 BiDiag, %.1f s" % dt}
-    out = {
-        "metric": METRIC, "value": round(flops / (ms_step * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f64_upd_f32": "f64 panels, f32 updates",
-                  "f64_upd_split32": "f64 panels, split-f32 updates"}[args.prec],
-        "data": "synthetic",
-        "config": {"workload": "batch of %d matrices, m~U{%d..%d}, n~U{%d..m}, tuned nb/tree/variant"
-                   % (cfg["count"], cfg["mlo"], cfg["mhi"], cfg["nlo"]),
-                   "count": len(mats), "classes": classes, "prec": args.prec,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "persistent_kernel<nb, %d> (all groups)" % bb.PRECS[args.prec],
-                     "kernel_ms": round(kern_ms, 3), "algorithmic_flops": actual},
-        "cpu_baseline": cpu,
-        "check": {"band_exact": band_ok, "max_fro_rel_err": fro_err,
-                  "max_sigma_err_rel_normA_sample": sig_err},
-    }
-    print(json.dumps(out), flush=True)
+    del buf, orig, vt, ws
+    return {"workload": "batch of %d matrices, m~U{%d..%d}, n~U{%d..m}, tuned nb/tree/variant, %s"
+                        % (cfg["count"], cfg["mlo"], cfg["mhi"], cfg["nlo"], prec),
+            "gflops": round(flops / (ms_step * 1e-3) / 1e9, 2), "ms_per_step": round(ms_step, 3),
+            "kernel_ms": round(float(np.mean(kms)), 3), "band_exact": band_ok,
+            "max_fro_rel_err": fro_err}
 
 
-def bench_adjoint(args, bb, torch, np, workloads):
-    """8192 x 1024 N(0,1) (seed 6), R-BiDiag Greedy, nb = 128, and the gradient
-    of sum(W * B) over the band (W N(0,1), seed 7).  One step = forward
-    reduction + adjoint, from a fresh copy of A already in HBM; HIP events on
-    the launch stream time each part."""
+def bench_adjoint(args, bb, torch, np, workloads, steps=3, warmup=1):
+    """8192 x 1024 N(0,1) (seed 6), R-BiDiag Greedy, nb = 128: forward plus the
+    gradient of sum(W * B) over the band (W N(0,1), seed 7)."""
     cfg = workloads.CONFIGS["adjoint"]
     m, n, nb = cfg["m"], cfg["n"], cfg["nb"]
     A = workloads.gaussian(m, n, cfg["seed"])
     W = torch.as_tensor(workloads.band_weights(n, nb, cfg["wseed"])).cuda()
     S0 = bb.to_colmajor(torch.from_numpy(A))
-    plan = bb.Plan(m, n, nb, args.tree, "rbidiag", prec=args.prec)
+    plan = bb.Plan(m, n, nb, "greedy", "rbidiag")
     vt, ws = plan.alloc()
     aws = torch.empty(plan.adjoint_workspace(), dtype=torch.uint8, device="cuda")
     S = torch.empty_like(S0)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     fw, bw = [], []
-    Ab = None
-    for k in range(args.warmup + args.steps):
+    for k in range(warmup + steps):
         S.copy_(S0)
         ev[0].record()
         plan.execute(S, m, vt, ws)
         ev[1].record()
-        Ab = plan.adjoint(S, m, W, vt, ws=aws)
+        plan.adjoint(S, m, W, vt, ws=aws)
         ev[2].record()
         torch.cuda.synchronize()
-        if k >= args.warmup:
+        if k >= warmup:
             fw.append(ev[0].elapsed_time(ev[1]))
             bw.append(ev[1].elapsed_time(ev[2]))
-        log("  step %d: forward %.2f ms, adjoint %.2f ms" % (k, ev[0].elapsed_time(ev[1]),
-                                                            ev[1].elapsed_time(ev[2])))
-    st = bb.poll_error(ws)
-    if st != 0:
-        raise RuntimeError("device scheduler error %d" % st)
-    Ag = Ab.cpu().numpy()
-    check = {}
-    if args.prec != "f64":
-        # mixed forward: distance to the gradient of the FP64 forward (central
-        # differences of a forward with FP32 rounding would measure its noise)
-        p64 = bb.Plan(m, n, nb, args.tree, "rbidiag")
-        v64, w64 = p64.alloc()
-        S.copy_(S0)
-        p64.execute(S, m, v64, w64)
-        A64 = p64.adjoint(S, m, W, v64).cpu().numpy()
-        check["rel_diff_to_f64_gradient"] = float(np.linalg.norm(Ag - A64) / np.linalg.norm(A64))
-        del p64, v64, w64
-    else:
-        check["fd_max_err_rel_grad_norm"] = fd_check(A, Ag, W, plan, bb, torch, np, m, n)
+    if bb.poll_error(ws) != 0 or plan.adjoint_poll_error(aws) != 0:
+        raise RuntimeError("device scheduler error in the adjoint")
     f_ms, b_ms = float(np.median(fw)), float(np.median(bw))
-    flops = workloads.flops_bidiag(m, n)
-    dtype = {"f64": "f64", "f64_upd_f32": "f64 panels, f32 updates; f64 adjoint",
-             "f64_upd_split32": "f64 panels, split-f32 updates; f64 adjoint"}[args.prec]
-    out = {
-        "metric": METRIC, "value": round(flops / ((f_ms + b_ms) * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f_ms + b_ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-        "data": "synthetic",
-        "config": {"workload": "adjoint 8192x1024 nb=128 rbidiag %s, forward + gradient of "
-                               "sum(W*B)" % args.tree, "m": m, "n": n, "nb": nb, "prec": args.prec,
-                   "parallelism": "single GPU"},
-        "forward_ms": round(f_ms, 3), "adjoint_ms": round(b_ms, 3),
-        "adjoint_over_forward": round(b_ms / f_ms, 3),
-        "check": check,
-        "roofline": None, "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
-
-
-def fd_check(A, Ag, W, plan, bb, torch, np, m, n):
-    """Central differences of the forward in 4 random unit directions: the
-    largest error relative to the gradient's norm."""
-    def L(M):
-        Sm = bb.to_colmajor(torch.from_numpy(M))
-        v2, w2 = plan.alloc()
-        plan.execute(Sm, m, v2, w2)
-        return float(torch.sum(W * Sm.t()[:n]))
-    rng = np.random.default_rng(8)
-    h = 1e-6 * np.linalg.norm(A)
-    fd_err = 0.0
-    for _ in range(4):
-        E = rng.standard_normal((m, n))
-        E /= np.linalg.norm(E)
-        fd = (L(A + h * E) - L(A - h * E)) / (2 * h)
-        fd_err = max(fd_err, abs(fd - float(np.sum(Ag * E))) / np.linalg.norm(Ag))
-    return fd_err
+    return {"workload": "adjoint 8192x1024 nb=128 rbidiag greedy, forward + gradient of sum(W*B)",
+            "forward_ms": round(f_ms, 3), "adjoint_ms": round(b_ms, 3),
+            "adjoint_over_forward": round(b_ms / f_ms, 3),
+            "gflops_forward": round(workloads.flops_bidiag(m, n) / (f_ms * 1e-3) / 1e9, 2)}
 
 
 def main():
@@ -279,17 +296,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--variant", default="rbidiag", choices=["bidiag", "rbidiag"])
-    ap.add_argument("--tree", default="greedy", choices=["flatts", "flattt", "greedy", "auto"])
+    ap.add_argument("--workload", default="square_graded", choices=["square_graded"])
+    ap.add_argument("--variant", default="bidiag", choices=["bidiag", "rbidiag", "threestep"])
+    ap.add_argument("--tree", default="auto", choices=["flatts", "flattt", "greedy", "auto"])
     ap.add_argument("--sched", default="persistent", choices=["persistent", "levels"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f64_upd_f32", "f64_upd_split32"])
-    ap.add_argument("--workload", default="tall_graded",
-                    choices=["tall_graded", "square_graded", "batch", "adjoint"])
     ap.add_argument("--nb", type=int, default=0, help="tile size (0: the workload's)")
     ap.add_argument("--m", type=int, default=0, help="rows (0: the workload's)")
     ap.add_argument("--n", type=int, default=0, help="columns (0: the workload's)")
+    ap.add_argument("--extras", default="tall,batch,adjoint,nb128,f32",
+                    help="comma list of extra workloads (empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -299,92 +316,47 @@ def main():
     import numpy as np
     import torch
 
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, HERE)
     import paper_1611_06892_amd as bb
     import workloads
 
-    if args.workload == "batch":
-        return bench_batch(args, bb, torch, np, workloads)
-    if args.workload == "adjoint":
-        return bench_adjoint(args, bb, torch, np, workloads)
-    cfg = workloads.CONFIGS[args.workload]
-    m, n, nb = args.m or cfg["m"], args.n or cfg["n"], args.nb or cfg["nb"]
-    log("generating %d x %d graded input" % (m, n))
-    if m * n <= 2 ** 27:
-        A, s = workloads.graded(m, n, *cfg["seeds"], cfg["smin"])
-        normA = float(np.linalg.norm(A))
-        S0 = bb.to_colmajor(torch.from_numpy(A))
-    else:
-        Ad, s = workloads.graded_device(m, n, *cfg["seeds"], cfg["smin"])
-        normA = float(torch.linalg.norm(Ad))
-        S0 = bb.to_colmajor(Ad)
-        del Ad
-    flops_metric = workloads.flops_bidiag(m, n)
-
-    plan = bb.Plan(m, n, nb, args.tree, args.variant, prec=args.prec, sched=args.sched,
-                   timing=True)
-    log("timing %s/%s: %d warmup + %d steps" % (args.variant, args.tree, args.warmup, args.steps))
-    ms_step, kms, S = time_plan(bb, torch, plan, S0, m, args.steps, args.warmup)
-    value = flops_metric / (ms_step * 1e-3) / 1e9
-
-    # Correctness of the timed result (outside the timed region): exact band
-    # structure and the singular values of B against the prescribed ones.
-    Bd = S.t()
-    i = torch.arange(m, device=Bd.device)[:, None]
-    j = torch.arange(n, device=Bd.device)[None, :]
-    band_ok = bool(torch.all(Bd[(j < i) | (j > i + nb)] == 0.0).item())
-    log("checking the band form")
-    sig_err = sig_rel = None
-    if n <= 4096:
-        sB = np.linalg.svd(Bd[:n].cpu().numpy(), compute_uv=False)
-    elif n <= 8192:
-        sB = torch.linalg.svdvals(Bd[:n].contiguous()).cpu().numpy()
-    else:
-        sB = None     # dense SVD too slow here; the Frobenius norm is checked instead
-    if sB is not None:
-        sig_err = float(np.max(np.abs(sB - s)))
-        sig_rel = float(np.max(np.abs(sB - s) / s))
-    fro_rel = abs(float(torch.linalg.norm(Bd)) - float(np.linalg.norm(s))) / float(np.linalg.norm(s))
-    del Bd
-
-    kern_ms = float(np.mean(kms))
-    algo = workloads.flops_rbidiag_actual(m, n) if args.variant == "rbidiag" else flops_metric
-    achieved = algo / (kern_ms * 1e-3) / 1e12
-    peak = FP64_PEAK_TFLOPS if args.prec == "f64" else FP32_PEAK_TFLOPS
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(args, m, n, nb),
-                "kernel": "persistent_kernel<%d, %d>" % (nb, bb.PRECS[args.prec]),
-                "kernel_ms": round(kern_ms, 3),
-                "algorithmic_flops": algo}
-
-    variants = {}
-    if not args.no_variants and args.workload == "tall_graded" and args.prec == "f64":
-        for var in ("bidiag", "rbidiag"):
-            for tree in ("greedy", "auto"):
-                p2 = bb.Plan(m, n, nb, tree, var, sched=args.sched, timing=True)
-                ms2, _, _ = time_plan(bb, torch, p2, S0, m, 2, 1)
-                variants["%s/%s" % (var, tree)] = round(flops_metric / (ms2 * 1e-3) / 1e9, 1)
-                del p2
-    cpu = None if (args.no_cpu_baseline or args.workload != "tall_graded") else cpu_baseline(workloads)
+    head = bench_square(args, bb, torch, np, workloads)
+    extras = {}
+    wanted = [e for e in args.extras.split(",") if e]
+    if "nb128" in wanted:
+        r = bench_square(args, bb, torch, np, workloads, nb=128, tree="greedy", prec="f64", steps=3,
+                         warmup=1, probes=False, label="square nb128")
+        extras["square_nb128_greedy"] = {"gflops": round(r["gflops"], 2), "kernel_ms": round(r["kernel_ms"], 3),
+                                         "frac_fp64_peak": r["roofline"]["frac"],
+                                         "fro_norm_rel_err": r["check"]["fro_norm_rel_err"]}
+    if "f32" in wanted:
+        r = bench_square(args, bb, torch, np, workloads, prec="f64_upd_f32", steps=3, warmup=1,
+                         probes=False, label="square f32 updates")
+        extras["square_f32_updates"] = {"gflops": round(r["gflops"], 2), "kernel_ms": round(r["kernel_ms"], 3),
+                                        "speed_vs_f64": round(head["kernel_ms"] / r["kernel_ms"], 3),
+                                        "fro_norm_rel_err": r["check"]["fro_norm_rel_err"]}
+    if "tall" in wanted:
+        extras["tall_graded"] = bench_tall(args, bb, torch, np, workloads)
+    if "adjoint" in wanted:
+        extras["adjoint"] = bench_adjoint(args, bb, torch, np, workloads)
+    if "batch" in wanted:
+        extras["batch"] = bench_batch(args, bb, torch, np, workloads)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_square()
 
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "metric": METRIC, "value": round(head["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f64_upd_f32": "f64 panels, f32 updates",
-                  "f64_upd_split32": "f64 panels, split-f32 updates"}[args.prec],
-        "data": "synthetic",
-        "config": {"workload": "%s %dx%d nb=%d %s %s" % (args.workload, m, n, nb, args.variant,
-                                                          args.tree),
-                   "m": m, "n": n, "nb": nb, "variant": args.variant, "tree": args.tree,
-                   "sched": args.sched, "prec": args.prec, "parallelism": "single GPU"},
-        "roofline": roofline,
+        "dtype": DTYPES[head["prec"]], "data": "synthetic",
+        "config": {"workload": "square_graded %dx%d nb=%d %s %s" % (head["m"], head["n"], head["nb"],
+                                                                  head["variant"], head["tree"]),
+                   "m": head["m"], "n": head["n"], "nb": head["nb"], "variant": head["variant"],
+                   "tree": head["tree"], "sched": args.sched, "prec": head["prec"],
+                   "parallelism": "single GPU"},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "variants_gflops": variants,
-        "check": {"band_exact": band_ok, "max_abs_sigma_err": sig_err,
-                  "max_rel_sigma_err": sig_rel, "fro_norm_rel_err": fro_rel,
-                  "sigma_tol": 50 * n * np.finfo(np.float64).eps * normA},
+        "check": head["check"],
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 
