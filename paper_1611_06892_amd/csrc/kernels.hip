@@ -44,7 +44,10 @@ struct Shape {
     static constexpr int LDL = NB + 1;                 // LDS stride of the leaf (odd: conflict-free)
     // doubles used by a panel: leaf buffer(s) (two at nb = 256), then the
     // reflector broadcast, taus, G, T_b and R1's diagonal entries
-    static constexpr int PANEL = (NB > 128 ? 32 : 16) * LDL + 2 * NB + 16 + 768;
+    // (nb = 256: two leaf buffers, the block's reflector ring, taus, G, two
+    // T_b and the role counters)
+    static constexpr int PANEL = NB > 128 ? 32 * LDL + 16 * NB + 16 + 256 + 512 + 2048 + 4
+                                          : 16 * LDL + 2 * NB + 16 + 768;
     static constexpr int UPDATE = 2 * (16 * LDL + 256);           // ... and by an update
     static constexpr int LDS = PANEL > UPDATE ? PANEL : UPDATE;
 };
@@ -777,32 +780,72 @@ __device__ __forceinline__ void panel_resident(const KArgs& a, const DevTask& tk
     }
 }
 
-// Panel for nb = 256 (16 column tiles of 256 x 16; one tile takes half of a
-// wave's register budget, so the tile cannot stay resident next to the
-// leaf).  The leaf works on an LDS copy of its column tile as above; the
-// trailing tiles are streamed instead: in block b each wave loads the tiles
-// J > b it owns (J = w and J = w + 8, a fixed assignment), applies Q_b^T
-// and stores them back.  Every lane reads back only the elements it stored
-// itself, so the stores need no fence.  Tile b + 1 goes to the second leaf
-// buffer in LDS instead of memory, where the next leaf reads it.
+// Synchronization inside one workgroup through LDS words, for code where the
+// waves of the workgroup follow different paths (no workgroup barrier).
+// wait_geq: wait until *f >= target; false once the watchdog has expired
+// (the error word is then set and the caller gives up).  post: make this
+// wave's earlier LDS writes visible, then add 1 to *f.
+__device__ __forceinline__ bool wait_geq(const int* f, int target, const KArgs& a) {
+    uint64_t t0 = 0;
+    for (int spin = 0;; ++spin) {
+        const int v = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (v >= target) break;
+        // the clock (a scalar memory read) only every 128 polls
+        if ((spin & 127) == 0) {
+            const uint64_t t = wall_clock64();
+            if (spin == 0) {
+                t0 = t;
+            } else if ((int64_t)(t - t0) > a.watchdog_ticks) {
+                if ((threadIdx.x & 63) == 0)
+                    __hip_atomic_store(&a.ctrl[CTRL_ERROR], 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    return true;
+}
+
+__device__ __forceinline__ void post(int* f) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Panel for nb = 256 (16 column tiles of 256 x 16, each taking half of a
+// wave's registers, so no tile can stay resident next to the leaf).  The
+// waves split into two roles that run side by side and meet only through
+// LDS counters:
+//  - leaf role (waves 0-3): factors block b from the LDS copy of column
+//    tile b.  Columns are handed on through a per-column counter instead of
+//    a workgroup barrier; the 16 reflectors of the block stay in an LDS ring.
+//    Then it writes U_b (explicit), the record's V, and R or zeros.
+//  - tile role (waves 4-7): forms T_b from the dot products (each 16-lane row
+//    of T on its own), then applies Q_b^T first to tile b + 1, which it hands
+//    to the next leaf through LDS (look-ahead), and then to the other tiles
+//    right of b, which it streams from and back to memory.  Tile J always
+//    goes to wave 4 + J % 4, so every lane reads back only what it stored.
+// The leaf of block b + 1 therefore runs while the tile role is still
+// applying block b to tiles b + 2 ... 15.
 template <int NB, int KIND, bool CO>
-__device__ __forceinline__ void panel_stream(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
+__device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
     using S = Shape<NB>;
     constexpr int MT = S::MT, LDL = S::LDL;
-    static_assert(MT == 16, "two tiles per wave");
     constexpr int SR = NB / 16;
     constexpr bool PAIR = KIND != K_GEQRT;
     constexpr bool TT = KIND == K_TTQRT;
-    double* Lf0 = lds;                      // leaf buffers: NB x 16, stride LDL, alternating by block
-    double* vbuf = lds + 32 * LDL;
-    double* taus = vbuf + 2 * NB;
-    double* Gs = taus + 16;
-    double* TbT = Gs + 256;
-    double* R1s = TbT + 256;
+    double* buf0 = lds;                     // column tile of the leaf, by block parity: NB x 16, stride LDL
+    double* vring = lds + 32 * LDL;         // the 16 reflectors of the current block, NB each
+    double* taus = vring + 16 * NB;
+    double* Gs = taus + 16;                 // G(l, c) at l + 16 c
+    double* TbT0 = Gs + 256;                // T_b (T(k, i) at i + 16 k), by block parity
+    double* Wpart = TbT0 + 512;             // the four tile waves' partial W, by tile parity
+    int* flags = (int*)(Wpart + 2 * 1024);  // counters
+    static_assert(32 * LDL + 16 * NB + 16 + 256 + 512 + 2048 + 4 <= S::LDS, "LDS layout");
+    enum { F_COL = 0, F_LEAF = 1, F_TB = 2, F_TILE = 3, F_WA = 4, F_WORDS = 8 };
     const int tid = threadIdx.x, lane = tid & 63, j = lane & 15, g = lane >> 4;
     const int lj = tid >> 4, lq = tid & 15;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool lw = w < 4;                  // waves 0-3 run the leaf, waves 4-7 form T_b
 
     const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
     const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
@@ -810,35 +853,122 @@ __device__ __forceinline__ void panel_stream(const KArgs& a, const DevTask& tk, 
     double* gV = rec;
     double* gTt = rec + NB * NB;
 
-    // column tile 0 into the first leaf buffer (8 elements per thread)
+    // column tile 0 into the first leaf buffer; counters to zero
 #pragma unroll
     for (int k = 0; k < NB * 16 / NT; ++k) {
         const int e = tid + NT * k, r = e % NB, c = e / NB;
-        Lf0[r + c * LDL] = TX.get(r, c);
+        buf0[r + c * LDL] = TX.get(r, c);
     }
-    if (PAIR && lw) R1s[tid] = T1.get(lq, lj);
-    retire(a, prev);
+    if (tid < F_WORDS) flags[tid] = 0;
+    retire(a, prev);                        // (a workgroup barrier)
+    lds_barrier();
 
-    for (int b = 0; b < MT; ++b) {
-        double* Lf = Lf0 + (b & 1) * 16 * LDL;
-        double* Ln = Lf0 + ((b + 1) & 1) * 16 * LDL;
-        if (lw) Gs[tid] = 0.0;
-        lds_barrier();
-
-        // 1. Leaf (waves 0-3), T_b one column behind (waves 4-7).
-        double x[SR];
-        double r1 = 0.0, til = 0.0;
-        if (lw) {
+    if (w < 4) {
+        // ---- leaf role -------------------------------------------------
+        double r1 = PAIR ? T1.get(lq, lj) : 0.0;
+        for (int b = 0; b < MT; ++b) {
+            if (!wait_geq(&flags[F_TILE], 4 * b, a)) break;     // column tile b is in its buffer
+            double* Lf = buf0 + (b & 1) * 16 * LDL;
+            double x[SR];
 #pragma unroll
             for (int s = 0; s < SR; ++s) x[s] = Lf[(lq + 16 * s) + lj * LDL];
-            if (PAIR) r1 = R1s[tid];
-            leaf_block<NB, KIND, 0, 8>(b, true, x, r1, til, vbuf, taus, Gs, lj, lq);
-            leaf_block<NB, KIND, 8, 8>(b, true, x, r1, til, vbuf, taus, Gs, lj, lq);
-        } else {
-            leaf_block<NB, KIND, 0, 8>(b, false, x, r1, til, vbuf, taus, Gs, lj, lq);
-            leaf_block<NB, KIND, 8, 8>(b, false, x, r1, til, vbuf, taus, Gs, lj, lq);
-        }
-        if (lw) {
+            bool ok = true;
+            auto leaf = [&](auto bc) {
+                constexpr int B = decltype(bc)::value;
+                constexpr int S0 = PAIR ? 0 : B;        // live slots [S0, S1)
+                constexpr int S1 = TT ? B + 1 : SR;
+                constexpr int NL = S1 - S0;
+                for (int c = 0; c < 16 && ok; ++c) {
+                    double* vb = vring + c * NB;
+                    if (lj == c) {
+                        auto tail = [&](int s) {
+                            if (!PAIR) return s > B || lq > c;
+                            if (TT) return s < B || lq <= c;
+                            return true;
+                        };
+                        constexpr int NQ = NL < 4 ? NL : 4;
+                        double q[NQ], al = 0.0;
+#pragma unroll
+                        for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) {
+                            const int s = S0 + k;
+                            if (tail(s)) q[k % NQ] = fma(x[s], x[s], q[k % NQ]);
+                        }
+                        if (!PAIR && lq == c) al = x[B];
+#pragma unroll
+                        for (int h = 1; h < NQ; h *= 2)
+#pragma unroll
+                            for (int k = 0; k + h < NQ; k += 2 * h) q[k] += q[k + h];
+                        if (PAIR && lq == c) al = r1;
+                        const double ss = sum16(q[0]);
+                        al = readlane64(al, 16 * (c & 3) + c);
+                        double tau = 0.0, beta = al, scale = 0.0;
+                        if (ss != 0.0) {
+                            const double nrm = refined_sqrt(fma(al, al, ss));
+                            beta = al >= 0.0 ? -nrm : nrm;
+                            const double d = al - beta;
+                            const double inv = refined_rcp(beta * d);
+                            tau = -(d * d) * inv;
+                            scale = beta * inv;
+                        }
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) {
+                            const int s = S0 + k;
+                            double vv;
+                            if (!PAIR && s == B) {
+                                const bool t = lq > c, dg = lq == c;
+                                if (t) x[s] *= scale;
+                                if (dg) x[s] = beta;
+                                vv = t ? x[s] : (dg ? 1.0 : 0.0);
+                            } else if (TT && s == B) {
+                                const bool t = lq <= c;
+                                if (t) x[s] *= scale;
+                                vv = t ? x[s] : 0.0;
+                            } else {
+                                x[s] *= scale;
+                                vv = x[s];
+                            }
+                            vb[lq + 16 * s] = vv;
+                        }
+                        if (PAIR && lq == c) r1 = beta;
+                        if (lq == 0) taus[c] = tau;
+                    }
+                    if (w == (c >> 2)) post(&flags[F_COL]);            // the owner wave
+                    if (!wait_geq(&flags[F_COL], 16 * b + c + 1, a)) { ok = false; break; }
+                    if (lj != c) {
+                        const double tc = taus[c];
+                        double vv[SR];
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) vv[S0 + k] = vb[lq + 16 * (S0 + k)];
+                        double dp[2] = {0.0, 0.0};
+#pragma unroll
+                        for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
+                        double d = dp[0] + dp[1];
+                        if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
+                        d = sum16(d);
+                        if (lj > c) {
+                            const double wv = tc * d;
+#pragma unroll
+                            for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
+                            if (PAIR && lq == c) r1 -= wv;
+                        } else if (lq == 0) {
+                            Gs[lj + 16 * c] = d;            // u_lj . u_c
+                        }
+                    }
+                }
+            };
+            switch (b) {
+#define BB_LEAF_CASE(K) case K: leaf(std::integral_constant<int, K>{}); break;
+                BB_LEAF_CASE(0) BB_LEAF_CASE(1) BB_LEAF_CASE(2) BB_LEAF_CASE(3)
+                BB_LEAF_CASE(4) BB_LEAF_CASE(5) BB_LEAF_CASE(6) BB_LEAF_CASE(7)
+                BB_LEAF_CASE(8) BB_LEAF_CASE(9) BB_LEAF_CASE(10) BB_LEAF_CASE(11)
+                BB_LEAF_CASE(12) BB_LEAF_CASE(13) BB_LEAF_CASE(14)
+                default: leaf(std::integral_constant<int, 15>{}); break;
+#undef BB_LEAF_CASE
+            }
+            if (!ok) break;
+            // R1's next diagonal entry: no block before b + 1 changes it
             double r1n = 0.0;
             if (PAIR && b + 1 < MT) r1n = T1.get(16 * (b + 1) + lq, 16 * (b + 1) + lj);
             const int col = 16 * b + lj;
@@ -853,86 +983,109 @@ __device__ __forceinline__ void panel_stream(const KArgs& a, const DevTask& tk, 
                 TX.put<CO>(row, col, PAIR ? 0.0 : (row <= col ? x[s] : 0.0));
             }
             if (PAIR) T1.put<CO>(16 * b + lq, 16 * b + lj, r1);
-            if (PAIR && b + 1 < MT) R1s[tid] = r1n;
+            r1 = r1n;
+            post(&flags[F_LEAF]);                                   // U_b, taus, G complete
         }
-        lds_barrier();
+    } else {
+        // ---- tile role -------------------------------------------------
+        // Wave u always handles rows 64u .. 64u + 63 of every tile (the same
+        // lanes load and store the same elements), so tiles need no
+        // memory fence between the waves; the 16 x 16 products W are summed
+        // over the four waves through LDS.
+        const int u = w - 4;
+        const int ti = lj - 16;             // this thread's row of T_b (and l = lq)
+        constexpr int RG = MT / 4;          // row tiles per wave
+        int nt = 0;                         // tiles processed so far (same sequence in all four waves)
+        bool ok = true;
+        for (int b = 0; b < MT && ok; ++b) {
+            if (!wait_geq(&flags[F_LEAF], 4 * (b + 1), a)) break;
+            const double* U = buf0 + (b & 1) * 16 * LDL;
+            double* TbT = TbT0 + (b & 1) * 256;
+            // T_b by the forward recurrence (each 16-lane row of T on its
+            // own), from G and tau read once
+            double gcol[16], tcol[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) {
+                gcol[cc] = Gs[lq + 16 * cc];
+                tcol[cc] = taus[cc];
+            }
+            double til = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) {
+                const double sm = sum16((lq >= ti && lq < cc) ? til * gcol[cc] : 0.0);
+                const double tic = cc < ti ? 0.0 : (cc == ti ? tcol[cc] : -tcol[cc] * sm);
+                if (lq == cc) til = tic;
+            }
+            TbT[lq + 16 * ti] = til;
+            gstore<CO>(gTt + 256 * b + (tid - 256), til);
+            post(&flags[F_TB]);
+            if (!wait_geq(&flags[F_TB], 4 * (b + 1), a)) break;
 
-        // 2. Trailing update of the tiles right of block b, at most two per
-        // wave: W = R1 + U_b^T X, W = T_b^T W, X -= U_b W.
-        auto tile_step = [&](int J, bool act, bool first) {
-            SCHED_FENCE();
-            d4 xt[MT];
-            d4 R1b = {0.0, 0.0, 0.0, 0.0};
-            if (act) {
-                load_slice<MT>(TX, 16 * J, xt);
-                if (PAIR) R1b = load16(T1, 16 * b, 16 * J);
-            }
-            d4 W = R1b;
+            // Tiles b + 1 (first: the next leaf's tile, handed on in LDS),
+            // then b + 2 .. 15 (back to memory): W = R1 + U_b^T X,
+            // W = T_b^T W, X -= U_b W.
+#pragma unroll 1
+            for (int J = b + 1; J < MT; ++J) {
+                asm volatile("" ::: "memory");
+                d4 R1b = {0.0, 0.0, 0.0, 0.0};
+                if (PAIR && u == 0) R1b = load16(T1, 16 * b, 16 * J);
+                d4 xr[RG];
 #pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const bool rows = (PAIR || i >= b) && (!TT || i <= b);
-                if (act && rows) {
-                    double la[4];
+                for (int k = 0; k < RG; ++k) xr[k] = load16(TX, 16 * (RG * u + k), 16 * J);
+                d4 W = R1b;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) la[r] = Lf[(16 * i + 4 * r + g) + j * LDL];
+                for (int k = 0; k < RG; ++k) {
+                    const int i = RG * u + k;
+                    if ((PAIR || i >= b) && (!TT || i <= b)) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) W = mfma(la[r], xt[i][r], W);
+                        for (int r = 0; r < 4; ++r) W = mfma(U[(16 * i + 4 * r + g) + j * LDL], xr[k][r], W);
+                    }
                 }
-                if (i & 1) SCHED_FENCE();
-            }
-            if (first) {
-                if (!lw) {
-                    t_step(til, 15, taus, Gs, lj, lq);
-                    TbT[lq + 16 * (lj - 16)] = til;     // T(i, l)
-                    gstore<CO>(gTt + 256 * b + (tid - 256), til);
-                }
-                lds_barrier();
-            }
-            if (act) {
+                double* Wp = Wpart + (nt & 1) * 1024;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Wp[256 * u + 64 * r + lane] = W[r];
+                post(&flags[F_WA]);
+                if (!wait_geq(&flags[F_WA], 4 * (nt + 1), a)) { ok = false; break; }
+                ++nt;
+                d4 Ws = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Ws[r] += Wp[256 * v + 64 * r + lane];
                 d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
-                if (PAIR) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
+                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], Ws[r], W2);
+                if (PAIR && u == 0) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
 #pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    if (!PAIR && i < b) continue;
-                    if (TT && i > b) continue;
-                    double lu[4];
+                for (int k = 0; k < RG; ++k) {
+                    const int i = RG * u + k;
+                    if ((PAIR || i >= b) && (!TT || i <= b)) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) lu[r] = -Lf[(16 * i + j) + (4 * r + g) * LDL];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) xt[i] = mfma(lu[r], W2[r], xt[i]);
-                    if (i & 1) SCHED_FENCE();
+                        for (int r = 0; r < 4; ++r)
+                            xr[k] = mfma(-U[(16 * i + j) + (4 * r + g) * LDL], W2[r], xr[k]);
+                    }
                 }
                 if (J == b + 1) {
-                    // the next leaf's column tile
+                    double* Ln = buf0 + ((b + 1) & 1) * 16 * LDL;
 #pragma unroll
-                    for (int i = 0; i < MT; ++i)
+                    for (int k = 0; k < RG; ++k)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) Ln[(16 * i + 4 * r + g) + j * LDL] = xt[i][r];
+                        for (int r = 0; r < 4; ++r) Ln[(16 * (RG * u + k) + 4 * r + g) + j * LDL] = xr[k][r];
+                    post(&flags[F_TILE]);                           // the next leaf may start
                 } else {
-                    store_slice<CO, MT>(TX, 16 * J, xt);
+#pragma unroll
+                    for (int k = 0; k < RG; ++k) store16<CO>(TX, 16 * (RG * u + k), 16 * J, xr[k]);
                 }
             }
-        };
-        // Round 0 takes tile b + 1 (wave (b + 1) % 8) and every wave's
-        // first remaining tile; round 1 the second tile of the waves that
-        // still own two.
-        // (a loop kept rolled: the two rounds' tiles are never live together)
-#pragma unroll 1
-        for (int k = 0; k < 2; ++k) {
-            const int J = k == 0 ? (w > b ? w : w + 8) : w + 8;
-            const bool act = (k == 0 || w > b) && J < MT && J > b;
-            tile_step(J, act, k == 0);
         }
-        lds_barrier();
     }
+    lds_barrier();
 }
 
 template <int NB, int KIND, bool CO>
 __device__ __forceinline__ void panel(const KArgs& a, const DevTask& tk, double* lds, Prev& prev) {
     if constexpr (NB <= 128) panel_resident<NB, KIND, CO>(a, tk, lds, prev);
-    else panel_stream<NB, KIND, CO>(a, tk, lds, prev);
+    else panel_split<NB, KIND, CO>(a, tk, lds, prev);
 }
 
 // ---------------------------------------------------------------------------
