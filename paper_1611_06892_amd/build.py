@@ -39,8 +39,8 @@ def _jobs():
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *common]
     jobs = []
     kern = os.path.join(CSRC, "kernels.hip")
-    for nb in TILE_SIZES:
-        for prec in PRECS + (1,):       # 1: the application kernels
+    for nb in (0,) + TILE_SIZES:        # 0: the kernels of batches mixing tile sizes 32 .. 128
+        for prec in PRECS + ((1,) if nb else ()):       # 1: the application kernels
             obj = os.path.join(OBJDIR, "kernels_nb%d_p%d.o" % (nb, prec))
             jobs.append((obj, [*device, "-DBB_KERNELS_NB=%d" % nb, "-DBB_KERNELS_PREC=%d" % prec,
                                "-c", kern, "-o", obj]))

@@ -96,7 +96,14 @@ struct bb_plan {
     // unit order of the chosen schedule, batched descriptors' sources.
     HostBlob blob;
     size_t off_tasks = 0, off_ndeps = 0, off_succ_off = 0, off_succ_idx = 0, off_units = 0;
-    size_t off_gidx = 0, off_dims = 0;
+    size_t off_gidx = 0, off_dims = 0, off_recoff = 0;
+    // Batched plans: per local matrix, its tile size (NB_MIXED plans), the
+    // first global slot of its records and their offset in the group's
+    // record area (doubles); vt_doubles: that area's size.
+    std::vector<int32_t> mat_nb;
+    std::vector<int32_t> slot_base;
+    std::vector<int64_t> recoff;
+    int64_t vt_doubles = -1;
     std::atomic<uint32_t> used_devices{0};   // devices an upload was enqueued on (bit mask)
     std::once_flag ev_once;
     hipError_t ev_err = hipSuccess;
@@ -177,13 +184,25 @@ bool validate(const bb_plan& P) {
     return true;
 }
 
+// Cost of task t in the GPU cost model.  In a launch that mixes tile sizes a
+// task is weighted by (nb / 128)^1.5: small tiles are latency bound, so their
+// time falls more slowly than their flops (nb^3).
+double task_cost(const bb_plan& P, int t) {
+    const bb::Task& x = P.g.tasks[t];
+    double c = kGpuCost[x.kind];
+    if (!P.mat_nb.empty()) c *= std::pow(P.mat_nb[x.mat] / 128.0, 1.5);
+    return c;
+}
+
 int build_schedule(bb_plan& P) {
     const bb::Graph& g = P.g;
     const int nt = (int)g.tasks.size();
-    P.ns = bbk::strip_width(P.nb);
+    // one strip per update below nb = 128 (every task of a mixed launch)
+    P.ns = P.nb == bbk::NB_MIXED ? 128 : bbk::strip_width(P.nb);
+    const int nb = P.nb == bbk::NB_MIXED ? 128 : P.nb;
     P.nparts.assign(nt, 1);
     for (int t = 0; t < nt; ++t)
-        if (!bb::is_panel(g.tasks[t].kind)) P.nparts[t] = (P.nb + P.ns - 1) / P.ns;
+        if (!bb::is_panel(g.tasks[t].kind)) P.nparts[t] = (nb + P.ns - 1) / P.ns;
     P.ndeps.assign(nt, 0);
     std::vector<int32_t> cnt(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
@@ -205,7 +224,7 @@ int build_schedule(bb_plan& P) {
     for (int t = nt - 1; t >= 0; --t) {
         double b = 0.0;
         for (int s = P.succ_off[t]; s < P.succ_off[t + 1]; ++s) b = std::max(b, blevel[P.succ_idx[s]]);
-        blevel[t] = b + kGpuCost[g.tasks[t].kind];
+        blevel[t] = b + task_cost(P, t);
     }
     // Plain bottom levels for both variants: ranking R-BiDiag's second phase
     // above QR(p,q) measured slightly slower for tall and square inputs.
@@ -238,7 +257,7 @@ int build_schedule(bb_plan& P) {
             int t = std::get<1>(r);
             P.units_ticket.push_back(t);
             P.units_ticket.push_back(std::get<2>(r));
-            running.emplace(now + kGpuCost[g.tasks[t].kind], t);
+            running.emplace(now + task_cost(P, t), t);
             busy++;
         }
         if (running.empty()) break;
@@ -303,6 +322,7 @@ size_t ws_blob_off(const bb_plan& P) {
 size_t ws_bytes_of(const bb_plan& P) { return ws_blob_off(P) + round_up(P.blob.bytes, 256); }
 
 size_t vt_bytes_of(const bb_plan& P) {
+    if (P.vt_doubles >= 0) return (size_t)P.vt_doubles * sizeof(double);
     return (size_t)P.g.nslots * (size_t)bbk::record_doubles(P.nb) * sizeof(double);
 }
 
@@ -321,13 +341,18 @@ int build_blob(bb_plan& P) {
     P.off_units = off; off = round_up(off + units.size() * 4, 256);
     P.off_gidx = off; off = round_up(off + P.gidx.size() * 8, 256);
     P.off_dims = off; off = round_up(off + P.dims.size() * 8, 256);
+    P.off_recoff = off; off = round_up(off + P.recoff.size() * 8, 256);
     if (!P.blob.alloc(off)) return BB_ENOMEM;
     char* h = P.blob.p;
     bbk::DevTask* dt = (bbk::DevTask*)(h + P.off_tasks);
     for (size_t t = 0; t < nt; ++t) {
         const bb::Task& s = P.g.tasks[t];
-        dt[t] = P.transposed ? bbk::DevTask{s.kind, s.trans ^ 1, s.c1, s.r1, s.c2, s.r2, s.slot, s.mat}
-                             : bbk::DevTask{s.kind, s.trans, s.r1, s.c1, s.r2, s.c2, s.slot, s.mat};
+        // slot within the task's matrix; tile-size code in trans >> 1
+        const int32_t slot = s.slot - (P.slot_base.empty() ? 0 : P.slot_base[s.mat]);
+        int32_t code = 0;
+        if (!P.mat_nb.empty()) code = P.mat_nb[s.mat] == 32 ? 0 : P.mat_nb[s.mat] == 64 ? 1 : 2;
+        dt[t] = P.transposed ? bbk::DevTask{s.kind, (s.trans ^ 1) | (code << 1), s.c1, s.r1, s.c2, s.r2, slot, s.mat}
+                             : bbk::DevTask{s.kind, s.trans | (code << 1), s.r1, s.c1, s.r2, s.c2, slot, s.mat};
     }
     auto put32 = [&](size_t o, const std::vector<int32_t>& v) {
         if (!v.empty()) std::memcpy(h + o, v.data(), v.size() * 4);
@@ -341,6 +366,7 @@ int build_blob(bb_plan& P) {
     put32(P.off_units, units);
     put64(P.off_gidx, P.gidx);
     put64(P.off_dims, P.dims);
+    put64(P.off_recoff, P.recoff);
     return BB_OK;
 }
 
@@ -383,12 +409,11 @@ int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipSt
     bbk::KArgs a{};
     if (d0) {
         a.single = *d0;
+        a.single.rec = (double*)vt;
         a.mats = nullptr;
     } else {
         a.mats = (const bbk::MatDesc*)((char*)ws + ws_mats_off());
     }
-    a.vt = (double*)vt;
-    a.slot_stride = bbk::record_doubles(P.nb);
     char* blob = (char*)ws + ws_blob_off(P);
     a.tasks = (const bbk::DevTask*)(blob + P.off_tasks);
     a.nunits = (int32_t)(P.units_ticket.size() / 2);
@@ -1187,25 +1212,42 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
         B->rec_off.assign(count, 0);
         B->nrec.assign(count, 0);
         const size_t wsg = 256;
-        for (int tile : {32, 64, 128, 256}) {
+        // Tile sizes 32 .. 128 share one launch when the batch holds more
+        // than one of them (tasks carry their size); nb = 256 runs apart.
+        std::vector<std::vector<int>> sets;
+        {
+            bool has[4] = {false, false, false, false};
+            for (int64_t i = 0; i < count; ++i)
+                has[B->nb[i] == 32 ? 0 : B->nb[i] == 64 ? 1 : B->nb[i] == 128 ? 2 : 3] = true;
+            const int small = (int)has[0] + (int)has[1] + (int)has[2];
+            if (small > 1) sets.push_back({32, 64, 128});
+            else
+                for (int k = 0; k < 3; ++k)
+                    if (has[k]) sets.push_back({32 << k});
+            if (has[3]) sets.push_back({256});
+        }
+        for (const std::vector<int>& set : sets) {
             std::vector<int64_t> idx;
             for (int64_t i = 0; i < count; ++i)
-                if (B->nb[i] == tile) idx.push_back(i);
-            if (idx.empty()) continue;
+                if (std::find(set.begin(), set.end(), B->nb[i]) != set.end()) idx.push_back(i);
             bb_plan* P = new bb_plan();
             bb_batch::Group grp;
-            grp.nb = tile;
+            grp.nb = set.size() > 1 ? bbk::NB_MIXED : set[0];
             grp.plan = P;
             B->groups.push_back(grp);       // owned by B from here on
-            P->nb = tile;
+            P->nb = grp.nb;
             P->prec = prec;
             P->opts = o;
             P->nmats = (int32_t)idx.size();
             P->gidx = idx;
             P->dims.resize(2 * idx.size());
-            const size_t rec_bytes = (size_t)bbk::record_doubles(tile) * sizeof(double);
+            P->slot_base.resize(idx.size());
+            P->recoff.resize(idx.size());
+            if (P->nb == bbk::NB_MIXED) P->mat_nb.resize(idx.size());
+            int64_t rec_doubles = 0;
             for (size_t li = 0; li < idx.size(); ++li) {
                 const int64_t i = idx[li];
+                const int tile = B->nb[i];
                 P->dims[2 * li] = B->m[i];
                 P->dims[2 * li + 1] = B->n[i];
                 bb::PlanOptions po;
@@ -1235,10 +1277,15 @@ int bb_batch_create(bb_batch** batch, int64_t count, const int64_t* m, const int
                     }
                 }
                 B->nrec[i] = gi.nslots;
-                B->rec_off[i] = (int64_t)P->g.nslots * (int64_t)rec_bytes;   // within the group
+                B->rec_off[i] = rec_doubles * (int64_t)sizeof(double);   // within the group
+                P->slot_base[li] = P->g.nslots;
+                P->recoff[li] = rec_doubles;
+                if (!P->mat_nb.empty()) P->mat_nb[li] = tile;
+                rec_doubles += (int64_t)gi.nslots * bbk::record_doubles(tile);
                 bb::append_graph(P->g, gi, (int32_t)li);
                 if (P->g.tasks.size() > (size_t)INT32_MAX / 2) { delete B; return BB_ENOTSUP; }
             }
+            P->vt_doubles = rec_doubles;
             int rc = finish_plan(*P);
             if (rc != BB_OK) { delete B; return rc; }
         }
@@ -1314,7 +1361,8 @@ int bb_batch_execute(bb_batch* B, double* const* A, const int64_t* lda, void* vt
         char* blob = w + ws_blob_off(P);
         if (bbk::launch_batch_desc((bbk::MatDesc*)(w + ws_mats_off()), P.nmats,
                                    (const int64_t*)(blob + P.off_gidx), (const int64_t*)(blob + P.off_dims),
-                                   A, lda, s) != hipSuccess)
+                                   (const int64_t*)(blob + P.off_recoff), A, lda, (double*)((char*)vt + grp.vt_off),
+                                   s) != hipSuccess)
             return BB_EHIP;
     }
     if (timed && hipEventRecord(B->ev0, s) != hipSuccess) return BB_EHIP;

@@ -118,20 +118,26 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 __device__ __forceinline__ MatDesc mat_desc(const KArgs& a, int mat) {
     if (a.mats == nullptr) return a.single;
     const uint64_t* w = reinterpret_cast<const uint64_t*>(a.mats + mat);
-    uint64_t f[4];
+    uint64_t f[5];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 5; ++k)
         f[k] = uniform64(__hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     MatDesc d;
     d.A = reinterpret_cast<double*>(f[0]);
     d.lda = (int64_t)f[1];
     d.m = (int64_t)f[2];
     d.n = (int64_t)f[3];
+    d.rec = reinterpret_cast<double*>(f[4]);
     return d;
 }
 
-__device__ __forceinline__ TileView view(const KArgs& a, const DevTask& tk, int pr, int pc, int nb) {
-    const MatDesc d = mat_desc(a, tk.mat);
+// The V/T record of a task (slot within its matrix's records).
+template <int NB>
+__device__ __forceinline__ double* record(const MatDesc& d, const DevTask& tk) {
+    return d.rec + (int64_t)tk.slot * (int64_t)(NB * NB + 16 * NB);
+}
+
+__device__ __forceinline__ TileView view(const MatDesc& d, const DevTask& tk, int pr, int pc, int nb) {
     const int trans = tk.trans & 1;
     TileView t;
     t.base = d.A + (int64_t)pr * nb + (int64_t)pc * nb * d.lda;
@@ -507,9 +513,6 @@ __device__ __forceinline__ void leaf_columns(bool lw, double (&x)[NB / 16], doub
     constexpr int S0 = PAIR ? 0 : B;        // live slots [S0, S1)
     constexpr int S1 = TT ? B + 1 : SR;
     constexpr int NL = S1 - S0;
-    // At nb = 256 the reflector is read again for the update instead of
-    // being held across the reduction (register budget).
-    constexpr bool REREAD = SR > 8;
     for (int c = 0; c < 16; ++c) {
         double* vb = vbuf + (c & 1) * NB;
         if (lw && lj == c) {
@@ -596,18 +599,11 @@ __device__ __forceinline__ void leaf_columns(bool lw, double (&x)[NB / 16], doub
                 for (int k = 0; k < NL; ++k) dp[k & 1] = fma(vv[S0 + k], x[S0 + k], dp[k & 1]);
                 double d = dp[0] + dp[1];
                 if (PAIR && lj > c && lq == c) d += r1;     // e_c meets row c of R1
-                if (REREAD) SCHED_FENCE();
                 d = sum16(d);
                 if (lj > c) {
                     const double wv = tc * d;
-                    if (REREAD) {
-                        SCHED_FENCE();
 #pragma unroll
-                        for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vb[lq + 16 * (S0 + k)];
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
-                    }
+                    for (int k = 0; k < NL; ++k) x[S0 + k] -= wv * vv[S0 + k];
                     if (PAIR && lq == c) r1 -= wv;
                 } else if (lq == 0) {
                     Gs[lj + 16 * c] = d;            // u_lj . u_c
@@ -662,9 +658,10 @@ __device__ __forceinline__ void panel_resident(const KArgs& a, const DevTask& tk
     const bool lw = tid < 256;              // waves 0-3 run the leaf, waves 4-7 form T_b
     const bool own = w < MT;                // the wave holds column tile w
 
-    const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
-    const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
-    double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
+    const MatDesc md = mat_desc(a, tk.mat);
+    const TileView T1 = view(md, tk, tk.r1, tk.c1, NB);
+    const TileView TX = PAIR ? view(md, tk, tk.r2, tk.c2, NB) : T1;
+    double* rec = record<NB>(md, tk);
     double* gV = rec;
     double* gTt = rec + NB * NB;
 
@@ -791,6 +788,7 @@ __device__ __forceinline__ bool wait_geq(const int* f, int target, const KArgs& 
         const int v = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
         if (v >= target) break;
+        __builtin_amdgcn_s_sleep(1);        // leave issue slots to the working waves
         // the clock (a scalar memory read) only every 128 polls
         if ((spin & 127) == 0) {
             const uint64_t t = wall_clock64();
@@ -847,9 +845,10 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
     const int lj = tid >> 4, lq = tid & 15;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    const TileView T1 = view(a, tk, tk.r1, tk.c1, NB);
-    const TileView TX = PAIR ? view(a, tk, tk.r2, tk.c2, NB) : T1;
-    double* rec = a.vt + (int64_t)tk.slot * a.slot_stride;
+    const MatDesc md = mat_desc(a, tk.mat);
+    const TileView T1 = view(md, tk, tk.r1, tk.c1, NB);
+    const TileView TX = PAIR ? view(md, tk, tk.r2, tk.c2, NB) : T1;
+    double* rec = record<NB>(md, tk);
     double* gV = rec;
     double* gTt = rec + NB * NB;
 
@@ -1103,11 +1102,12 @@ __device__ __forceinline__ void update(const KArgs& a, const DevTask& tk, int pa
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, w = tid >> 6;
     const int c0 = part * NS + 16 * w;
-    const TileView T2 = view(a, tk, tk.r2, tk.c2, NB);
-    const TileView T1 = HASC1 ? view(a, tk, tk.r1, tk.c1, NB) : T2;
+    const MatDesc md = mat_desc(a, tk.mat);
+    const TileView T2 = view(md, tk, tk.r2, tk.c2, NB);
+    const TileView T1 = HASC1 ? view(md, tk, tk.r1, tk.c1, NB) : T2;
     // Waves without columns still take part in staging and barriers.
     const bool active = 16 * w < NS && c0 < T2.vc;
-    const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
+    const Rec rec(record<NB>(md, tk), NB);
 
     d4 c2[MT];
     if (active) load_slice<MT>(T2, c0, c2);
@@ -1183,10 +1183,11 @@ __device__ __forceinline__ void update32(const KArgs& a, const DevTask& tk, int 
     constexpr bool HASC1 = KIND != K_UNMQR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 15, g = lane >> 4;
     const int c0 = part * NS + 16 * w;
-    const TileView T2 = view(a, tk, tk.r2, tk.c2, NB);
-    const TileView T1 = HASC1 ? view(a, tk, tk.r1, tk.c1, NB) : T2;
+    const MatDesc md = mat_desc(a, tk.mat);
+    const TileView T2 = view(md, tk, tk.r2, tk.c2, NB);
+    const TileView T1 = HASC1 ? view(md, tk, tk.r1, tk.c1, NB) : T2;
     const bool active = 16 * w < NS && c0 < T2.vc;
-    const Rec rec(a.vt + (int64_t)tk.slot * a.slot_stride, NB);
+    const Rec rec(record<NB>(md, tk), NB);
     float* fl = reinterpret_cast<float*>(lds);
 
     auto fetch = [&](int b, double (&pre)[PRE]) {
@@ -1328,15 +1329,38 @@ __device__ __forceinline__ void run_unit(const KArgs& a, int task, int part, dou
     retire(a, prev);               // a kind that ran nothing
 }
 
+// A unit of a launch that mixes tile sizes: the task's own size, from its
+// descriptor.
+template <bool CO, int PREC>
+__device__ __forceinline__ void run_unit_mixed(const KArgs& a, int task, int part, double* lds, Prev& prev,
+                                               int* sch) {
+    const int code = __builtin_amdgcn_readfirstlane(a.tasks[task].trans) >> 1;
+    switch (code) {
+    case 0: run_unit<32, CO, PREC>(a, task, part, lds, prev, sch); break;
+    case 1: run_unit<64, CO, PREC>(a, task, part, lds, prev, sch); break;
+    default: run_unit<128, CO, PREC>(a, task, part, lds, prev, sch); break;
+    }
+}
+
+template <int NB, bool CO, int PREC>
+__device__ __forceinline__ void run_any(const KArgs& a, int task, int part, double* lds, Prev& prev, int* sch) {
+    if constexpr (NB == NB_MIXED) run_unit_mixed<CO, PREC>(a, task, part, lds, prev, sch);
+    else run_unit<NB, CO, PREC>(a, task, part, lds, prev, sch);
+}
+
+// LDS of a kernel (doubles): the mixed kernels hold the largest size they run.
+template <int NB>
+constexpr int kernel_lds() { return NB == NB_MIXED ? Shape<128>::LDS : Shape<NB>::LDS; }
+
 }  // namespace
 
 // One launch per topological level: block b runs unit unit_base + b.
 template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
-    __shared__ double lds[Shape<NB>::LDS];
+    __shared__ double lds[kernel_lds<NB>()];
     const int2 u = a.units[unit_base + blockIdx.x];
     Prev none{-1, 0, 0, 0, 0};
-    run_unit<NB, false, PREC>(a, u.x, u.y, lds, none, nullptr);
+    run_any<NB, false, PREC>(a, u.x, u.y, lds, none, nullptr);
 }
 
 // Persistent scheduler.  The work units are listed in one priority order:
@@ -1355,8 +1379,8 @@ __global__ __launch_bounds__(NT) void level_kernel(KArgs a, int32_t unit_base) {
 
 template <int NB, int PREC>
 __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
-    __shared__ double lds[Shape<NB>::LDS + SCH_WORDS / 2];
-    int* sch = (int*)(lds + Shape<NB>::LDS);
+    __shared__ double lds[kernel_lds<NB>() + SCH_WORDS / 2];
+    int* sch = (int*)(lds + kernel_lds<NB>());
     const int tid = threadIdx.x;
     Prev prev{-1, 0, 0, 0, 0};
     if (tid == 0) sch[SCH_TICKET] = -2;     // -2: no ticket taken yet
@@ -1395,7 +1419,7 @@ __global__ __launch_bounds__(NT) void persistent_kernel(KArgs a) {
         // add, which would also wait for the previous unit's stores.
         asm volatile("buffer_inv sc1" ::: "memory");
         const uint64_t t_run = a.trace != nullptr && tid == 0 ? wall_clock64() : 0;
-        run_unit<NB, true, PREC>(a, un.x, un.y, lds, prev, sch);
+        run_any<NB, true, PREC>(a, un.x, un.y, lds, prev, sch);
         prev.task = un.x;
         prev.ticket = u;
         prev.wait = t_wait;
@@ -1420,19 +1444,21 @@ hipError_t launch_init(const KArgs& a, const int32_t* ndeps_init, int32_t ntasks
 }
 
 __global__ void batch_desc_kernel(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
-                                  double* const* A, const int64_t* lda) {
+                                  const int64_t* recoff, double* const* A, const int64_t* lda, double* vt) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmats; i += gridDim.x * blockDim.x) {
         const int64_t g = gidx[i];
-        mats[i] = MatDesc{A[g], lda[g], dims[2 * i], dims[2 * i + 1]};
+        mats[i] = MatDesc{A[g], lda[g], dims[2 * i], dims[2 * i + 1], vt + recoff[i]};
     }
 }
 
 hipError_t launch_batch_desc(MatDesc* mats, int32_t nmats, const int64_t* gidx, const int64_t* dims,
-                             double* const* A, const int64_t* lda, hipStream_t s) {
+                             const int64_t* recoff, double* const* A, const int64_t* lda, double* vt,
+                             hipStream_t s) {
     if (nmats <= 0) return hipSuccess;
     int blocks = (nmats + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(batch_desc_kernel, dim3(blocks), dim3(256), 0, s, mats, nmats, gidx, dims, A, lda);
+    hipLaunchKernelGGL(batch_desc_kernel, dim3(blocks), dim3(256), 0, s, mats, nmats, gidx, dims, recoff, A,
+                       lda, vt);
     return hipGetLastError();
 }
 
@@ -1491,6 +1517,9 @@ template hipError_t launch_persistent_np<BB_KERNELS_NB, BB_KERNELS_PREC>(const K
 #ifdef BB_KERNELS_COMMON
 #define BB_NP_CASES(F, ...)                                                        \
     switch (nb * 4 + prec) {                                                       \
+    case NB_MIXED * 4 + 0: return F<NB_MIXED, 0>(__VA_ARGS__);                     \
+    case NB_MIXED * 4 + 2: return F<NB_MIXED, 2>(__VA_ARGS__);                     \
+    case NB_MIXED * 4 + 3: return F<NB_MIXED, 3>(__VA_ARGS__);                     \
     case 32 * 4 + 0: return F<32, 0>(__VA_ARGS__);                                 \
     case 32 * 4 + 2: return F<32, 2>(__VA_ARGS__);                                 \
     case 32 * 4 + 3: return F<32, 3>(__VA_ARGS__);                                 \

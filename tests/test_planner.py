@@ -266,8 +266,8 @@ def test_apply_workspace_and_argument_errors():
 
 
 def test_batch_plan_layout_and_tuning_table():
-    """A batch is one graph per tile size; records of each matrix are
-    contiguous and the workspace covers every group."""
+    """Tile sizes 32 .. 128 of a batch share one graph (one launch); records
+    of each matrix are contiguous and the workspace covers every group."""
     shapes = [(300, 200), (64, 64), (1000, 100), (129, 33), (500, 500)]
     nbs = [64, 32, 128, 32, 64]
     plan = bb.BatchPlan(shapes, nb=nbs, tree=["greedy", "flatts", "auto", "flattt", "greedy"],
