@@ -86,6 +86,9 @@ struct bb_plan {
     std::vector<int32_t> level_off;          // units_level offsets per level
     double cp = 0.0, total = 0.0;
     double makespan = 0.0;                   // length of the list schedule (cost-model units)
+    // Panel scratch (nb = 256): one area per workgroup of a persistent
+    // launch, or per panel unit of the widest level (levels put panels first).
+    int64_t pscr_slots = 0;
     bool apply_graph = false;                // applies Q or P (bb_apply_q/p), no panels
     // m < n (Section 3.6): the graph reduces A^T, whose tile (i, j) is tile
     // (j, i) of A seen transposed; the device tasks swap the tile
@@ -295,18 +298,31 @@ int build_schedule(bb_plan& P) {
     for (size_t u = 0; u < nu; ++u) P.level_off[level[P.units_ticket[2 * u]] + 1]++;
     for (int l = 0; l < nlev; ++l) P.level_off[l + 1] += P.level_off[l];
     P.units_level.assign(2 * nu, 0);
+    // Within a level the panels come first, so that a panel's block index
+    // is also its scratch slot.
     std::vector<int32_t> lf(P.level_off.begin(), P.level_off.end() - 1);
-    for (size_t u = 0; u < nu; ++u) {
-        int t = P.units_ticket[2 * u];
-        int pos = lf[level[t]]++;
-        P.units_level[2 * pos] = t;
-        P.units_level[2 * pos + 1] = P.units_ticket[2 * u + 1];
+    std::vector<int32_t> npan(nlev, 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t u = 0; u < nu; ++u) {
+            int t = P.units_ticket[2 * u];
+            if (bb::is_panel(g.tasks[t].kind) != (pass == 0)) continue;
+            if (pass == 0) npan[level[t]]++;
+            int pos = lf[level[t]]++;
+            P.units_level[2 * pos] = t;
+            P.units_level[2 * pos + 1] = P.units_ticket[2 * u + 1];
+        }
+    P.pscr_slots = 0;
+    if (bbk::panel_scratch_doubles(P.nb) > 0 && !P.apply_graph) {
+        int32_t widest = 0;
+        for (int32_t c : npan) widest = std::max(widest, c);
+        P.pscr_slots = P.opts.sched == BB_SCHED_PERSISTENT ? std::max(1, P.opts.workgroups) : widest;
     }
     return validate(P) ? BB_OK : BB_EDAG;
 }
 
 // Workspace: control words, the launch's matrix descriptors, one dependency
-// counter per task, the trace (BB_FLAG_TRACE), then the copy of the graph.
+// counter per task, the trace (BB_FLAG_TRACE), the copy of the graph, then
+// the panels' scratch (nb = 256).
 size_t ws_mats_off() { return round_up(sizeof(int32_t) * bbk::CTRL_WORDS, 256); }
 size_t ws_deps_off(const bb_plan& P) {
     return ws_mats_off() + round_up(sizeof(bbk::MatDesc) * (size_t)P.nmats, 256);
@@ -319,7 +335,10 @@ size_t ws_blob_off(const bb_plan& P) {
     if (P.opts.flags & BB_FLAG_TRACE) b += round_up(4 * sizeof(int64_t) * (P.units_ticket.size() / 2), 256);
     return b;
 }
-size_t ws_bytes_of(const bb_plan& P) { return ws_blob_off(P) + round_up(P.blob.bytes, 256); }
+size_t ws_pscr_off(const bb_plan& P) { return ws_blob_off(P) + round_up(P.blob.bytes, 256); }
+size_t ws_bytes_of(const bb_plan& P) {
+    return ws_pscr_off(P) + (size_t)P.pscr_slots * (size_t)bbk::panel_scratch_doubles(P.nb) * sizeof(double);
+}
 
 size_t vt_bytes_of(const bb_plan& P) {
     if (P.vt_doubles >= 0) return (size_t)P.vt_doubles * sizeof(double);
@@ -425,6 +444,7 @@ int launch_kernels(bb_plan& P, const bbk::MatDesc* d0, void* vt, void* ws, hipSt
     const double khz = (double)device_attr(hipDeviceAttributeWallClockRate, 100000);
     a.watchdog_ticks = (int64_t)(P.opts.watchdog_s * khz * 1000.0);
     a.trace = (P.opts.flags & BB_FLAG_TRACE) ? (int64_t*)((char*)ws + ws_trace_off(P)) : nullptr;
+    a.pscratch = P.pscr_slots > 0 ? (double*)((char*)ws + ws_pscr_off(P)) : nullptr;
 
     const bool timed = allow_timing && (P.opts.flags & BB_FLAG_TIMING) != 0;
     if (timed && plan_events(P) != BB_OK) return BB_EHIP;

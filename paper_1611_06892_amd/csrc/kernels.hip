@@ -189,6 +189,11 @@ __device__ __forceinline__ void store16(const TileView& t, int r0, int c0, d4 x)
     for (int r = 0; r < 4; ++r) t.put<CO>(r0 + 4 * r + g, c0 + j, x[r]);
 }
 
+// Whole-vector accesses of 32 bytes (global memory).
+typedef __attribute__((address_space(1))) d4 gd4;
+__device__ __forceinline__ d4 load_d4(const double* p) { return *(const gd4*)p; }
+__device__ __forceinline__ void store_d4(double* p, d4 v) { *(gd4*)p = v; }
+
 // Reads of one V/T record through a buffer descriptor: every load of a
 // product shares one per-lane byte offset and adds a wave-uniform constant,
 // so unrolled products need no per-load address registers.  Reads past the
@@ -990,12 +995,32 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
         // Wave u always handles rows 64u .. 64u + 63 of every tile (the same
         // lanes load and store the same elements), so tiles need no
         // memory fence between the waves; the 16 x 16 products W are summed
-        // over the four waves through LDS.
+        // over the four waves through LDS.  Between blocks the tiles are kept
+        // in the panel's scratch (this workgroup's alone), each lane's 16
+        // values side by side, so every store writes whole cache lines; the
+        // matrix itself is read once per tile and written by the leaf.  The
+        // next tile is loaded while the current one is computed.
         const int u = w - 4;
         const int ti = lj - 16;             // this thread's row of T_b (and l = lq)
         constexpr int RG = MT / 4;          // row tiles per wave
         int nt = 0;                         // tiles processed so far (same sequence in all four waves)
         bool ok = true;
+        double* scr = a.pscratch + (int64_t)blockIdx.x * panel_scratch_doubles(NB) + 4 * lane;
+        auto scr_at = [&](int J, int k) { return scr + ((J * 4 + u) * RG + k) * 256; };
+        d4 xn[RG], R1n = {0.0, 0.0, 0.0, 0.0};
+        // tile Jn as block bn finds it: from the matrix for the first block,
+        // else from the scratch
+        auto fetch = [&](int bn, int Jn) {
+            if (PAIR && u == 0) R1n = load16(T1, 16 * bn, 16 * Jn);
+            if (bn == 0) {
+#pragma unroll
+                for (int k = 0; k < RG; ++k) xn[k] = load16(TX, 16 * (RG * u + k), 16 * Jn);
+            } else {
+#pragma unroll
+                for (int k = 0; k < RG; ++k) xn[k] = load_d4(scr_at(Jn, k));
+            }
+        };
+        fetch(0, 1);
         for (int b = 0; b < MT && ok; ++b) {
             if (!wait_geq(&flags[F_LEAF], 4 * (b + 1), a)) break;
             const double* U = buf0 + (b & 1) * 16 * LDL;
@@ -1026,20 +1051,22 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
 #pragma unroll 1
             for (int J = b + 1; J < MT; ++J) {
                 asm volatile("" ::: "memory");
-                d4 R1b = {0.0, 0.0, 0.0, 0.0};
-                if (PAIR && u == 0) R1b = load16(T1, 16 * b, 16 * J);
+                const d4 R1b = R1n;
                 d4 xr[RG];
 #pragma unroll
-                for (int k = 0; k < RG; ++k) xr[k] = load16(TX, 16 * (RG * u + k), 16 * J);
-                d4 W = R1b;
+                for (int k = 0; k < RG; ++k) xr[k] = xn[k];
+                if (J + 1 < MT) fetch(b, J + 1);
+                d4 Wk[2] = {R1b, {0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
                 for (int k = 0; k < RG; ++k) {
                     const int i = RG * u + k;
                     if ((PAIR || i >= b) && (!TT || i <= b)) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) W = mfma(U[(16 * i + 4 * r + g) + j * LDL], xr[k][r], W);
+                        for (int r = 0; r < 4; ++r)
+                            Wk[k & 1] = mfma(U[(16 * i + 4 * r + g) + j * LDL], xr[k][r], Wk[k & 1]);
                     }
                 }
+                const d4 W = Wk[0] + Wk[1];
                 double* Wp = Wpart + (nt & 1) * 1024;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Wp[256 * u + 64 * r + lane] = W[r];
@@ -1064,6 +1091,8 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
                             xr[k] = mfma(-U[(16 * i + j) + (4 * r + g) * LDL], W2[r], xr[k]);
                     }
                 }
+#pragma unroll
+                for (int k = 0; k < RG; ++k) store_d4(scr_at(J, k), xr[k]);
                 if (J == b + 1) {
                     double* Ln = buf0 + ((b + 1) & 1) * 16 * LDL;
 #pragma unroll
@@ -1071,11 +1100,10 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
 #pragma unroll
                         for (int r = 0; r < 4; ++r) Ln[(16 * (RG * u + k) + 4 * r + g) + j * LDL] = xr[k][r];
                     post(&flags[F_TILE]);                           // the next leaf may start
-                } else {
-#pragma unroll
-                    for (int k = 0; k < RG; ++k) store16<CO>(TX, 16 * (RG * u + k), 16 * J, xr[k]);
                 }
             }
+            // the first tile of the next block (stored above)
+            if (b + 2 < MT) fetch(b + 1, b + 2);
         }
     }
     lds_barrier();

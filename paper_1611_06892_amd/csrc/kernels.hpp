@@ -39,12 +39,18 @@ struct KArgs {
     int64_t watchdog_ticks;  // wall-clock ticks without progress before giving up
     int64_t* trace;          // NULL, or 4 int64 per unit (persistent mode):
                              // {ready-wait start, run start, run end, workgroup}
+    double* pscratch;        // nb = 256: panel scratch, panel_scratch_doubles(nb) per slot;
+                             // slot = workgroup (persistent) or block of the level launch
 };
 
 // Update strip width (columns of the logical C tile per work unit): one
 // 16-column slice per wave of the 512-thread workgroup, so the whole tile up
 // to nb = 128 and a 128-column half at nb = 256.
 inline int strip_width(int nb) { return nb < 128 ? nb : 128; }
+
+// Scratch of one nb = 256 panel: the trailing column tiles (nb x 16 each)
+// between blocks, in the order the workgroup's lanes hold them.
+__host__ __device__ inline int64_t panel_scratch_doubles(int nb) { return nb == 256 ? 16LL * nb * 16 : 0; }
 
 // One V/T record: V (nb x nb) and nb/16 blocks T_b^T (16 x 16).
 inline int64_t record_doubles(int nb) { return 1LL * nb * nb + 16LL * nb; }
