@@ -84,8 +84,15 @@ enum { BB_BIDIAG = 0, BB_RBIDIAG = 1, BB_QRONLY = 2, BB_THREESTEP = 3 };
  * product in FP32 and adds it into the FP64 tiles; BB_F64_UPD_SPLIT32 also
  * carries the FP32 rounding error of every operand (x = x_hi + x_lo), forms
  * A_hi B_hi + A_hi B_lo + A_lo B_hi, and accumulates 16-row chunks in FP64.
- * (Section 3.6 notes the tile codes exist in single and double precision;
- * the mixed forms are an extension.) */
+ * Accuracy: both modes reduce A + dA exactly with ||dA|| of order
+ * n eps_32 ||A||.  The split mode is NOT more accurate than BB_F64_UPD_F32:
+ * the FP32 matrix-core instruction rounds every product and its 4-term sum
+ * to FP32 before the FP64 chunk sum, so the hi x hi term alone carries FP32
+ * rounding; the split mode only lowers the Frobenius-norm (orthogonality)
+ * drift.  Neither mode is faster than BB_F64 at the measured sizes: panels,
+ * which bound the runtime, stay FP64.  All-FP32 data (FP32 matrices and
+ * panels) is not provided.  (Section 3.6 notes the tile codes exist in
+ * single and double precision; the mixed forms are an extension.) */
 enum { BB_F64 = 0, BB_F64_UPD_F32 = 2, BB_F64_UPD_SPLIT32 = 3 };
 /* Execution of the task graph: one persistent launch whose workgroups take
  * work units in a precomputed priority order (a list-scheduling simulation
@@ -155,7 +162,9 @@ void bb_plan_destroy(bb_plan* plan);
  *   ws_bytes : scheduler state (error flag, ticket and done counters, one
  *              dependency counter per task, the optional trace) followed by
  *              the copy of the task graph that each execution uploads
- *              (tasks, successor lists, unit order).  Contents are not kept
+ *              (tasks, successor lists, unit order) and, for nb = 256, the
+ *              panels' scratch (512 KiB per workgroup of a persistent launch,
+ *              or per panel of the widest level).  Contents are not kept
  *              between executions.
  */
 int bb_plan_workspace(const bb_plan* plan, size_t* vt_bytes, size_t* ws_bytes);
@@ -191,7 +200,8 @@ int bb_execute(bb_plan* plan, void* A, int64_t lda, void* vt, size_t vt_bytes, v
  * ends; the call itself allocates nothing (no hipMalloc, hipFree or
  * allocating library routine) and records no timing events.  A plan whose
  * bb_plan_workspace ws_bytes exceeds BB_NOALLOC_WS_MAX is rejected with
- * BB_EWORKSPACE.  Every call on a device shares that device's array, so
+ * BB_EWORKSPACE (every nb = 256 plan: its panel scratch alone exceeds it).
+ * Every call on a device shares that device's array, so
  * calls whose executions overlap on one device (other streams, other
  * threads) race; calls in one stream order do not.  Arguments as
  * bb_execute: plan (1), A (2), lda (3), vt (4), vt_bytes (5), stream (6).
@@ -267,8 +277,8 @@ int bb_apply_workspace(bb_plan* plan, int side, int transpose, int64_t ncols, si
  * with vt_bytes (7): that reduction's records; Abar (8) m x n device output,
  * ldabar (9) >= m; ws (10) / ws_bytes (11) >= bb_adjoint_workspace; stream
  * (12).  FP64.  The gradient exists where every diagonal and super-diagonal
- * block of B is nonsingular (true almost surely); BB_QRONLY plans and
- * plans with nb = 256 return BB_ENOTSUP.
+ * block of B is nonsingular (true almost surely); BB_QRONLY plans, plans
+ * with nb = 256 and plans of m < n (reduced as A^T) return BB_ENOTSUP.
  */
 int bidiag_band_adjoint(bb_plan* plan, const void* B, int64_t ldb, const void* W, int64_t ldw,
                         const void* vt, size_t vt_bytes, void* Abar, int64_t ldabar, void* ws,
@@ -285,10 +295,11 @@ int bb_adjoint_poll_error(bb_plan* plan, const void* ws, void* stream, int* devi
 /*
  * A batch reduces `count` independent matrices, each by its own task graph
  * (the graphs of Sections 3.4/3.5 for its own p x q tile grid, nb, tree and
- * variant).  The graphs of all matrices with the same nb are joined, without
- * edges between matrices, into one graph that one persistent launch
- * executes; the (at most three) tile sizes run one after the other on the
- * stream.  Sizes may differ freely (ragged tiles as in the single form).
+ * variant).  The graphs are joined, without edges between matrices, into one
+ * graph that one persistent launch executes; its tasks carry their own tile
+ * size (32, 64 or 128).  Matrices with nb = 256 form a second graph, launched
+ * after the first on the same stream.  Sizes may differ freely (ragged
+ * tiles as in the single form).
  */
 typedef struct bb_batch bb_batch;
 

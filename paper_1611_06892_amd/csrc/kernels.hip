@@ -230,10 +230,14 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
-// sqrt(t) and 1/x for positive normal t and nonzero normal x: the hardware
-// approximations refined by Newton steps (within an ulp, without the special
-// value and scaling paths of the IEEE library forms, which the Householder
-// steps never need).
+// sqrt(t) and 1/x for positive normal t and nonzero normal x, from the
+// hardware approximations (v_rsq_f64, v_rcp_f64):
+//  - sqrt: one step of Goldschmidt's coupled iteration for s ~ sqrt(t) and
+//    h ~ 1/(2 sqrt(t)) (residual e = 1/2 - h s, then s += s e, h += h e),
+//    followed by two Newton-Raphson corrections s += h (t - s^2);
+//  - 1/x: two Newton-Raphson steps r += r (1 - x r).
+// Both end within an ulp, without the special-value and scaling paths of the
+// IEEE library forms, which the Householder steps never need.
 __device__ __forceinline__ double refined_sqrt(double t) {
     const double r = __builtin_amdgcn_rsq(t);
     double s = t * r, h = 0.5 * r;

@@ -1,6 +1,6 @@
 """GPU tests of batched reductions (bb_batch_*): many independent matrices of
-different sizes, tile sizes, trees and variants in one persistent launch per
-tile size.
+different sizes, tile sizes, trees and variants in one persistent launch
+(tile sizes 32 to 128 share it; nb = 256 runs in a second).
 
 Every matrix is checked against the FP64 oracle (sign-normalized B, exact
 band), and against the same matrix reduced alone: a task computes the same
@@ -90,6 +90,45 @@ def test_tuned_batch_of_the_batch_recipe(bb):
         Bo, _ = oracle.band_reduce(A, nb)
         d = np.linalg.norm(oracle.sign_normalize(B, nb) - oracle.sign_normalize(Bo, nb))
         assert d <= 50 * A.shape[1] * EPS * np.linalg.norm(A), (i, A.shape, d)
+
+
+def size_class(m, n):
+    """The tuner's size class of an m x n matrix: row range and aspect
+    1000 n / m (the edges of the offline tuner)."""
+    m_edges, r_edges = [64, 192, 384, 640, 1025], [0, 250, 500, 1000]
+    ci = next(c for c in range(4) if m_edges[c] <= m < m_edges[c + 1])
+    a = 1000.0 * n / m
+    ri = next(r for r in range(3) if r_edges[r] < a <= r_edges[r + 1])
+    return ci, ri
+
+
+def test_full_batch_recipe_per_class_oracle_sample(bb):
+    """The whole batch recipe, 4096 matrices (m ~ U{64..1024}, n ~ U{32..m},
+    seed 5) in the launches of one plan with the tuned (nb, tree, variant):
+    every matrix exact band and Frobenius norm; the first two matrices of
+    each of the twelve size classes against the oracle."""
+    cfg = workloads.CONFIGS["batch"]
+    mats = workloads.batch_shapes(cfg["count"], cfg["seed"], cfg["mlo"], cfg["mhi"], cfg["nlo"])
+    print("full batch of", len(mats), flush=True)
+    plan, Bs = run_batch(bb, mats)
+    picked = {}
+    for i, (A, B) in enumerate(zip(mats, Bs)):
+        nb = plan.info(i)["nb"]
+        assert oracle.band_violation(B, nb) == 0.0, i
+        nA = np.linalg.norm(A)
+        assert abs(np.linalg.norm(B) - nA) <= 50 * A.shape[1] * EPS * nA, i
+        picked.setdefault(size_class(*A.shape), [])
+        if len(picked[size_class(*A.shape)]) < 2:
+            picked[size_class(*A.shape)].append(i)
+    assert len(picked) == 12
+    for cls, idx in sorted(picked.items()):
+        for i in idx:
+            A, B = mats[i], Bs[i]
+            nb = plan.info(i)["nb"]
+            print("class", cls, "matrix", i, A.shape, "nb", nb, flush=True)
+            Bo, _ = oracle.band_reduce(A, nb)
+            d = np.linalg.norm(oracle.sign_normalize(B, nb) - oracle.sign_normalize(Bo, nb))
+            assert d <= 50 * A.shape[1] * EPS * np.linalg.norm(A), (cls, i, A.shape, d)
 
 
 def test_batch_reuse_and_timing(bb):
