@@ -136,6 +136,16 @@ def graded_input(bb, torch, np, workloads, m, n, seeds, smin):
     return Ad, s
 
 
+def gaussian_input(torch, m, n, seed):
+    """m x n N(0,1) on the device from a seeded torch generator.  The
+    reduction's memory accesses do not depend on the values, so this input
+    stands in for the graded one where its generation (a device QR) cannot
+    run, as under hardware-counter collection."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    return torch.randn(m, n, generator=gen, device="cuda", dtype=torch.float64)
+
+
 def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, steps=None,
                  warmup=None, probes=True, label="square"):
     """The graded m x n square workload (default 16384^2): reduction timing,
@@ -148,9 +158,14 @@ def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, 
     variant = args.variant
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
-    log("generating %d x %d graded input" % (m, n))
-    Ad, s = graded_input(bb, torch, np, workloads, m, n, cfg["seeds"], cfg["smin"])
+    log("generating %d x %d %s input" % (m, n, args.input))
+    if args.input == "gaussian":
+        Ad = gaussian_input(torch, m, n, cfg["seeds"][0])
+        s = None
+    else:
+        Ad, s = graded_input(bb, torch, np, workloads, m, n, cfg["seeds"], cfg["smin"])
     nA = float(torch.linalg.norm(Ad))
+    ref = nA if s is None else float(np.linalg.norm(s))
     S0 = bb.to_colmajor(Ad)
     plan = bb.Plan(m, n, nb, tree, variant, prec=prec, sched=args.sched, timing=True,
                    watchdog_s=60.0)
@@ -160,7 +175,7 @@ def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, 
     i = torch.arange(m, device=B.device)[:, None]
     j = torch.arange(n, device=B.device)[None, :]
     band_ok = bool(torch.all(B[(j < i) | (j > i + nb)] == 0.0).item())
-    fro = abs(float(torch.linalg.norm(B)) - float(np.linalg.norm(s))) / float(np.linalg.norm(s))
+    fro = abs(float(torch.linalg.norm(B)) - ref) / ref
     probe = None
     if probes:
         gen = torch.Generator(device="cuda")
@@ -307,6 +322,9 @@ def main():
     ap.add_argument("--extras", default="tall,batch,adjoint,nb128,f32",
                     help="comma list of extra workloads (empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--input", default="graded", choices=["graded", "gaussian"],
+                    help="entries of the square workload: graded singular values (the workload), or "
+                         "N(0,1) of the same shape (same memory accesses; no device QR to build it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -348,8 +366,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPES[head["prec"]], "data": "synthetic",
-        "config": {"workload": "square_graded %dx%d nb=%d %s %s" % (head["m"], head["n"], head["nb"],
-                                                                  head["variant"], head["tree"]),
+        "config": {"workload": "square_%s %dx%d nb=%d %s %s" % (args.input, head["m"], head["n"], head["nb"],
+                                                               head["variant"], head["tree"]),
                    "m": head["m"], "n": head["n"], "nb": head["nb"], "variant": head["variant"],
                    "tree": head["tree"], "sched": args.sched, "prec": head["prec"],
                    "parallelism": "single GPU"},
