@@ -875,7 +875,7 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
         // ---- leaf role -------------------------------------------------
         double r1 = PAIR ? T1.get(lq, lj) : 0.0;
         for (int b = 0; b < MT; ++b) {
-            if (!wait_geq(&flags[F_TILE], 4 * b, a)) break;     // column tile b is in its buffer
+            if (!wait_geq(&flags[F_TILE], b, a)) break;         // column tile b is in its buffer
             double* Lf = buf0 + (b & 1) * 16 * LDL;
             double x[SR];
 #pragma unroll
@@ -996,35 +996,41 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
         }
     } else {
         // ---- tile role -------------------------------------------------
-        // Wave u always handles rows 64u .. 64u + 63 of every tile (the same
-        // lanes load and store the same elements), so tiles need no
-        // memory fence between the waves; the 16 x 16 products W are summed
-        // over the four waves through LDS.  Between blocks the tiles are kept
-        // in the panel's scratch (this workgroup's alone), each lane's 16
-        // values side by side, so every store writes whole cache lines; the
-        // matrix itself is read once per tile and written by the leaf.  The
-        // next tile is loaded while the current one is computed.
+        // Tile J belongs to wave 4 + J % 4 for the whole panel, which applies
+        // Q_b^T to it alone (W = R1 + U_b^T X over all rows, W = T_b^T W,
+        // X -= U_b W): no partial sums between waves.  Only the row tiles a
+        // block changes are loaded, updated and stored (all of them for TS;
+        // those at or below block b for GEQRT, at or above it in TTQRT's
+        // triangle), except for tile b + 1, which its owner hands to the next
+        // leaf whole, through LDS.  Between blocks the tiles wait in the
+        // panel's scratch (this workgroup's alone, each lane's values side by
+        // side, whole-line stores); a row tile comes from the matrix the first
+        // time a block changes it or the leaf needs it.  The next tile is
+        // loaded as soon as the current one is stored.
         const int u = w - 4;
         const int ti = lj - 16;             // this thread's row of T_b (and l = lq)
-        constexpr int RG = MT / 4;          // row tiles per wave
-        int nt = 0;                         // tiles processed so far (same sequence in all four waves)
         bool ok = true;
         double* scr = a.pscratch + (int64_t)blockIdx.x * panel_scratch_doubles(NB) + 4 * lane;
-        auto scr_at = [&](int J, int k) { return scr + ((J * 4 + u) * RG + k) * 256; };
-        d4 xn[RG], R1n = {0.0, 0.0, 0.0, 0.0};
-        // tile Jn as block bn finds it: from the matrix for the first block,
-        // else from the scratch
-        auto fetch = [&](int bn, int Jn) {
-            if (PAIR && u == 0) R1n = load16(T1, 16 * bn, 16 * Jn);
-            if (bn == 0) {
+        auto scr_at = [&](int J, int i) { return scr + (J * MT + i) * 256; };
+        auto active = [&](int i, int bb) { return PAIR ? (!TT || i <= bb) : i >= bb; };
+        // block in which row tile i is first changed
+        auto first = [&](int i) { return TT ? i : 0; };
+        d4 x[MT], R1b = {0.0, 0.0, 0.0, 0.0};
+        // tile J as block bb needs it
+        auto fetch = [&](int J, int bb) {
+            const bool whole = J == bb + 1;
+            if (PAIR) R1b = load16(T1, 16 * bb, 16 * J);
 #pragma unroll
-                for (int k = 0; k < RG; ++k) xn[k] = load16(TX, 16 * (RG * u + k), 16 * Jn);
-            } else {
-#pragma unroll
-                for (int k = 0; k < RG; ++k) xn[k] = load_d4(scr_at(Jn, k));
+            for (int i = 0; i < MT; ++i) {
+                if (!whole && !active(i, bb)) continue;
+                if (bb > first(i)) x[i] = load_d4(scr_at(J, i));
+                else x[i] = load16(TX, 16 * i, 16 * J);
             }
         };
-        fetch(0, 1);
+        // this wave's first tile after block bb (MT if none)
+        auto next_tile = [&](int bb) { return bb + 1 + ((u - (bb + 1)) % 4 + 4) % 4; };
+        int Jn = next_tile(0);
+        if (Jn < MT) fetch(Jn, 0);
         for (int b = 0; b < MT && ok; ++b) {
             if (!wait_geq(&flags[F_LEAF], 4 * (b + 1), a)) break;
             const double* U = buf0 + (b & 1) * 16 * LDL;
@@ -1049,65 +1055,47 @@ __device__ __forceinline__ void panel_split(const KArgs& a, const DevTask& tk, d
             post(&flags[F_TB]);
             if (!wait_geq(&flags[F_TB], 4 * (b + 1), a)) break;
 
-            // Tiles b + 1 (first: the next leaf's tile, handed on in LDS),
-            // then b + 2 .. 15 (back to memory): W = R1 + U_b^T X,
-            // W = T_b^T W, X -= U_b W.
 #pragma unroll 1
-            for (int J = b + 1; J < MT; ++J) {
+            for (int J = Jn; J < MT; J += 4) {
                 asm volatile("" ::: "memory");
-                const d4 R1b = R1n;
-                d4 xr[RG];
-#pragma unroll
-                for (int k = 0; k < RG; ++k) xr[k] = xn[k];
-                if (J + 1 < MT) fetch(b, J + 1);
+                const bool whole = J == b + 1;
                 d4 Wk[2] = {R1b, {0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-                for (int k = 0; k < RG; ++k) {
-                    const int i = RG * u + k;
-                    if ((PAIR || i >= b) && (!TT || i <= b)) {
+                for (int i = 0; i < MT; ++i) {
+                    if (!active(i, b)) continue;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            Wk[k & 1] = mfma(U[(16 * i + 4 * r + g) + j * LDL], xr[k][r], Wk[k & 1]);
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        Wk[i & 1] = mfma(U[(16 * i + 4 * r + g) + j * LDL], x[i][r], Wk[i & 1]);
                 }
                 const d4 W = Wk[0] + Wk[1];
-                double* Wp = Wpart + (nt & 1) * 1024;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Wp[256 * u + 64 * r + lane] = W[r];
-                post(&flags[F_WA]);
-                if (!wait_geq(&flags[F_WA], 4 * (nt + 1), a)) { ok = false; break; }
-                ++nt;
-                d4 Ws = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) Ws[r] += Wp[256 * v + 64 * r + lane];
                 d4 W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], Ws[r], W2);
-                if (PAIR && u == 0) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
+                for (int r = 0; r < 4; ++r) W2 = mfma(TbT[j + 16 * (4 * r + g)], W[r], W2);
+                if (PAIR) store16<CO>(T1, 16 * b, 16 * J, R1b - W2);
 #pragma unroll
-                for (int k = 0; k < RG; ++k) {
-                    const int i = RG * u + k;
-                    if ((PAIR || i >= b) && (!TT || i <= b)) {
+                for (int i = 0; i < MT; ++i) {
+                    if (!active(i, b)) continue;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            xr[k] = mfma(-U[(16 * i + j) + (4 * r + g) * LDL], W2[r], xr[k]);
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        x[i] = mfma(-U[(16 * i + j) + (4 * r + g) * LDL], W2[r], x[i]);
                 }
-#pragma unroll
-                for (int k = 0; k < RG; ++k) store_d4(scr_at(J, k), xr[k]);
-                if (J == b + 1) {
+                if (whole) {
                     double* Ln = buf0 + ((b + 1) & 1) * 16 * LDL;
 #pragma unroll
-                    for (int k = 0; k < RG; ++k)
+                    for (int i = 0; i < MT; ++i)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) Ln[(16 * (RG * u + k) + 4 * r + g) + j * LDL] = xr[k][r];
+                        for (int r = 0; r < 4; ++r) Ln[(16 * i + 4 * r + g) + j * LDL] = x[i][r];
                     post(&flags[F_TILE]);                           // the next leaf may start
+                } else {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i)
+                        if (active(i, b)) store_d4(scr_at(J, i), x[i]);
                 }
+                // the next tile: this block's, else the next block's first
+                const int Jnext = J + 4 < MT ? J + 4 : next_tile(b + 1);
+                if (Jnext < MT) fetch(Jnext, J + 4 < MT ? b : b + 1);
             }
-            // the first tile of the next block (stored above)
-            if (b + 2 < MT) fetch(b + 1, b + 2);
+            Jn = next_tile(b + 1);      // fetched above, after the block's last tile
         }
     }
     lds_barrier();
