@@ -155,10 +155,14 @@ const double kUnit[bb::NKINDS] = {4.0, 6.0, 2.0, 6.0, 12.0, 6.0, 6.0, 12.0, 6.0}
 // Execution-cost model used to order work on the GPU (relative latency of one
 // task with its column strips run side by side).  Unlike Table 1, whose unit
 // is flops, it reflects that a panel is a chain of nb dependent Householder
-// steps while an update is throughput-bound MFMA work (measured on MI355X for
-// nb = 128 in a loaded run: GEQRT / TSQRT / TTQRT panels ~100 / 135 / 120 us,
-// UNMQR / TSMQR / TTMQR tile updates ~41 / 60 / 53 us).
+// steps while an update is throughput-bound MFMA work.  Measured on MI355X in
+// loaded runs, in units of 10 us:
+//  - nb <= 128 (nb = 128): GEQRT / TSQRT / TTQRT panels ~100 / 135 / 120 us,
+//    UNMQR / TSMQR / TTMQR tile updates ~41 / 60 / 53 us;
+//  - nb = 256: panels ~397 / 506 / 353 us, updates (two 128-column halves
+//    side by side) ~104 / 176 / 116 us.
 const double kGpuCost[bb::NKINDS] = {10.0, 13.5, 12.0, 4.1, 6.0, 5.3, 4.1, 6.0, 5.3};
+const double kGpuCost256[bb::NKINDS] = {39.7, 50.6, 35.3, 10.4, 17.6, 11.6, 10.4, 17.6, 11.6};
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -192,7 +196,7 @@ bool validate(const bb_plan& P) {
 // time falls more slowly than their flops (nb^3).
 double task_cost(const bb_plan& P, int t) {
     const bb::Task& x = P.g.tasks[t];
-    double c = kGpuCost[x.kind];
+    double c = (P.nb == 256 ? kGpuCost256 : kGpuCost)[x.kind];
     if (!P.mat_nb.empty()) c *= std::pow(P.mat_nb[x.mat] / 128.0, 1.5);
     return c;
 }
