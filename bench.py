@@ -46,9 +46,10 @@ def time_plan(bb, torch, plan, S0, m, steps, warmup, label=""):
         S.copy_(S0)
         plan.execute(S, m, vt, ws)
         log("  %s warmup %d: %.2f ms" % (label, w, plan.last_kernel_ms()))
-    st = bb.poll_error(ws)
-    if st != 0:
-        raise RuntimeError("device scheduler error %d" % st)
+    if warmup:      # the status word is written by an execution; before one it is undefined
+        st = bb.poll_error(ws)
+        if st != 0:
+            raise RuntimeError("device scheduler error %d" % st)
     torch.cuda.synchronize()
     kms = []
     t0 = time.perf_counter()

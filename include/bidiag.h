@@ -375,7 +375,8 @@ int bidiag_band_batched(double* const* A, const int64_t* lda, int64_t count, con
  * bb_poll_error -- synchronize `stream` and read the scheduler's error word
  * from ws: *device_status = 0 if the last execution completed, else a BB_E*
  * code.  ws = NULL reads the word of the last bb_execute_noalloc on the
- * current device.  Returns BB_OK or BB_EHIP.
+ * current device.  The word is written by bb_execute; on a workspace that no
+ * execution has used yet its value is undefined.  Returns BB_OK or BB_EHIP.
  */
 int bb_poll_error(const void* ws, void* stream, int* device_status);
 
