@@ -428,6 +428,42 @@ double bb_critical_path(int p, int q, int tree, int variant, int auto_a, int wor
  */
 int bb_choose(int64_t m, int64_t n, int nb, const bb_opts* opts, int* tree, int* variant, double* estimate);
 
+/* ---- band to singular values (the GE2VAL pipeline, Sections 2 and 6.2) ----
+ * After the band reduction, the singular values of A are those of the n x n
+ * upper band B (m >= n; for m < n, of B^T).  The paper leaves the two
+ * remaining steps to any published method; here both run on the device.
+ *
+ * bb_bnd2bd -- BND2BD: reduce the upper band of bandwidth nb held in the
+ * leading n x n part of the column-major B (device, leading dimension ldb;
+ * only entries with 0 <= j - i <= nb are read, B is not written) to upper
+ * bidiagonal form U^T B V (U, V orthogonal, V e1 = e1, neither formed) by
+ * two-sided Householder bulge chasing, one row per sweep, the sweeps
+ * pipelined over the GPU in one persistent launch.  Writes the diagonal
+ * d[0..n-1] and the superdiagonal e[0..n-2] (device).  The diagonal and
+ * superdiagonal are those of the Golub-Kahan bidiagonalization of B started
+ * at e1, so they are unique up to signs.
+ * ws: device workspace of bb_bnd2bd_workspace bytes (control words, the band
+ * with room for the fill, 24 nb n bytes, and one progress counter per
+ * sweep), overwritten.  watchdog_s: seconds a sweep may wait for the one
+ * before it (0 = 30); when it fires the launch stops and bb_poll_error(ws)
+ * reports BB_ETIMEOUT.  Arguments: B (1), ldb >= max(1, n) (2), n >= 0 (3),
+ * 1 <= nb <= 256 (4), d (5), e (6), ws (7), ws_bytes (8, BB_EWORKSPACE when
+ * too small), watchdog_s (9), stream (10).  Asynchronous.
+ */
+int bb_bnd2bd_workspace(int64_t n, int nb, size_t* ws_bytes);
+int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
+              size_t ws_bytes, double watchdog_s, void* stream);
+
+/*
+ * bb_bd2val -- BD2VAL: the singular values of the upper bidiagonal with
+ * diagonal d[0..n-1] and superdiagonal e[0..n-2] (device), in decreasing
+ * order, into sigma[0..n-1] (device).  Bisection on the Sturm counts of the
+ * 2n x 2n Golub-Kahan tridiagonal, one singular value per thread, to an
+ * absolute accuracy of a few eps * ||B||.  Arguments: d (1), e (2), n >= 0
+ * (3), sigma (4), stream (5).  Asynchronous; no workspace.
+ */
+int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* stream);
+
 /* Drop every plan the one-shot entry points cache (bidiag_band, bb_query,
  * bidiag_band_batched).  Plans in use by a running call are released when
  * that call returns. */

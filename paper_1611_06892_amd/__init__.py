@@ -60,7 +60,7 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
            "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear",
-           "bb_execute_noalloc", "bb_choose"]
+           "bb_execute_noalloc", "bb_choose", "bb_bnd2bd_workspace", "bb_bnd2bd", "bb_bd2val"]
 
 
 def lib():
@@ -145,6 +145,12 @@ def lib():
     L.bb_choose.restype = i32
     L.bb_execute_noalloc.argtypes = [P, vp, i64, vp, ctypes.c_size_t, vp]
     L.bb_execute_noalloc.restype = i32
+    L.bb_bnd2bd_workspace.argtypes = [i64, i32, szp]
+    L.bb_bnd2bd_workspace.restype = i32
+    L.bb_bnd2bd.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, ctypes.c_double, vp]
+    L.bb_bnd2bd.restype = i32
+    L.bb_bd2val.argtypes = [vp, vp, i64, vp, vp]
+    L.bb_bd2val.restype = i32
     L.bb_cache_clear.argtypes = []
     L.bb_cache_clear.restype = None
     L.bb_plan_trace.argtypes = [P, szp, lp, ctypes.POINTER(ctypes.c_double), vp]
@@ -418,6 +424,60 @@ def band(A, nb, tree="auto", variant="bidiag", plan=None, check=True, **opts):
         if st != 0:
             raise BidiagError(st, "device scheduler")
     return S.t(), vt, plan
+
+
+def bnd2bd_workspace(n, nb) -> int:
+    """Workspace bytes of bnd2bd for an n x n band of bandwidth nb."""
+    b = ctypes.c_size_t()
+    _check(lib().bb_bnd2bd_workspace(int(n), int(nb), ctypes.byref(b)), "bb_bnd2bd_workspace")
+    return b.value
+
+
+def bnd2bd(S, ldb, n, nb, ws=None, watchdog_s=0.0, stream=None, check=True):
+    """Band to bidiagonal (bb_bnd2bd).  S: CUDA FP64 storage of a column-major
+    matrix whose leading n x n part holds the upper band of bandwidth nb
+    (leading dimension ldb), e.g. the storage tensor a Plan reduced.
+    Returns (d, e) as CUDA tensors; S is not modified."""
+    import torch
+    dev = S.device
+    if ws is None:
+        ws = torch.empty(max(bnd2bd_workspace(n, nb), 8), dtype=torch.uint8, device=dev)
+    d = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    _check(lib().bb_bnd2bd(ctypes.c_void_p(S.data_ptr()), int(ldb), int(n), int(nb),
+                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), float(watchdog_s),
+                           _stream_handle(stream)), "bb_bnd2bd")
+    if check:
+        st = poll_error(ws, stream)
+        if st != 0:
+            raise BidiagError(st, "bnd2bd sweep pipeline")
+    return d[:n], e[:max(n - 1, 0)]
+
+
+def bd2val(d, e, stream=None):
+    """Singular values of the upper bidiagonal (d, e) in decreasing order
+    (bb_bd2val), as a CUDA tensor."""
+    import torch
+    n = d.numel()
+    d = d.to(dtype=torch.float64).contiguous()
+    e = e.to(device=d.device, dtype=torch.float64).contiguous()
+    sigma = torch.empty(max(n, 1), dtype=torch.float64, device=d.device)
+    _check(lib().bb_bd2val(ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()), int(n),
+                           ctypes.c_void_p(sigma.data_ptr()), _stream_handle(stream)), "bb_bd2val")
+    return sigma[:n]
+
+
+def ge2val(A, nb, tree="auto", variant="bidiag", **opts):
+    """Singular values of A by GE2BND + BND2BD + BD2VAL, all on the GPU
+    (decreasing order, a CUDA tensor).  A is not modified."""
+    m, n = A.shape
+    if m < n:
+        return ge2val(A.t(), nb, tree, variant, **opts)
+    B, vt, plan = band(A, nb, tree, variant, **opts)
+    S = B.t()                      # the column-major storage, leading dimension m
+    d, e = bnd2bd(S, m, n, nb)
+    return bd2val(d, e)
 
 
 TREE_NAMES = {v: k for k, v in TREES.items()}

@@ -3,7 +3,8 @@
 The tile kernels are compiled once per (tile size, kernel family) pair (nb =
 32, 64, 128, 256; reductions with FP64, FP32 or split-FP32 updates, and the
 applications of Q and P) and once for their size-independent part, from the
-same source, in parallel with the host sources.
+same source, in parallel with the adjoint, the band-to-singular-value
+kernels and the host sources.
 
 Usage: python -m paper_1611_06892_amd.build   (or build() from Python)
 """
@@ -46,8 +47,9 @@ def _jobs():
                                "-c", kern, "-o", obj]))
     obj = os.path.join(OBJDIR, "kernels_common.o")
     jobs.append((obj, [*device, "-DBB_KERNELS_COMMON", "-c", kern, "-o", obj]))
-    obj = os.path.join(OBJDIR, "adjoint.o")
-    jobs.append((obj, [*device, "-c", os.path.join(CSRC, "adjoint.hip"), "-o", obj]))
+    for src in ("adjoint.hip", "ge2val.hip"):
+        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+        jobs.append((obj, [*device, "-c", os.path.join(CSRC, src), "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(OBJDIR, src + ".o")
         jobs.append((obj, [hipcc, *common, "-c", os.path.join(CSRC, src), "-o", obj]))

@@ -1,0 +1,491 @@
+// The two steps after the band reduction (the GE2VAL pipeline of Sections 2
+// and 6.2): BND2BD, band to bidiagonal by bulge chasing, and BD2VAL,
+// singular values of the bidiagonal, on gfx950.
+//
+// BND2BD.  The n x n upper band of bandwidth nb is copied into a band work
+// array with room for the fill of the chase (nb - 1 diagonals below the
+// main one, 2 nb - 1 above), column-major by diagonal offset:
+//     W[(i - j + 2 nb - 1) + j * 3 nb]  holds entry (i, j).
+// Sweep k clears row k beyond its superdiagonal and chases the bulge this
+// makes down the band, one block of nb columns per step.  Step t of sweep k
+// works at column c = k + 1 + t nb:
+//   * a reflector from the right clears row rr (rr = k for t = 0, else
+//     c - nb, the row the previous step filled) beyond column c; it is
+//     applied to rows rr+1 .. c+nb-1 of columns c .. c+nb-1;
+//   * a reflector from the left clears column c below the diagonal; it is
+//     applied to rows c .. c+nb-1 of columns c+1 .. c+2nb-1.
+// Only the first row or column of a bulge is cleared; the rest is cleared
+// by later sweeps.  Step t of sweep k+1 touches an entry that step t+2 of
+// sweep k also touches (row k+1+(t+1)nb, column k+1+(t+2)nb) and nothing of
+// a later step, so it may start once sweep k has finished step t+2: about a
+// third of the steps of a sweep separate consecutive sweeps, and n / (3 nb)
+// sweeps run at once.
+//
+// One persistent launch: each workgroup takes the next sweep (a ticket from
+// an atomic counter, so a sweep is only ever waited for by a later one that
+// a running workgroup holds: no deadlock for any grid) and runs its steps in
+// order, each after the previous sweep's progress counter allows it.  The
+// counter is published with agent-scope release fences in every wave before
+// a barrier, and read with an agent-scope acquire; a wall-clock watchdog
+// bounds every wait.
+//
+// BD2VAL.  The singular values of the bidiagonal (d, e) are the positive
+// eigenvalues of the 2n x 2n Golub-Kahan matrix, symmetric tridiagonal with
+// a zero diagonal and off-diagonal d1, e1, d2, ..., dn.  A Sturm count (the
+// signs of the pivots of T - x I, safeguarded against zero pivots) gives the
+// number of singular values below x; each thread bisects for one singular
+// value, so all n are found at once (the bisection method of the paper's
+// list of BD2VAL methods, chosen over the serial bidiagonal QR for its
+// parallelism).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "bidiag.h"
+
+namespace bbg {
+
+constexpr int NT = 256;                 // threads of the chase kernel (4 waves)
+constexpr int NW = NT / 64;
+constexpr int MAX_NB = 256;
+enum : int { G_ERROR = 1, G_HEAD = 32, G_WORDS = 64 };
+
+struct ChaseArgs {
+    double* W;
+    int64_t ldw;          // 3 nb
+    int64_t n;
+    int nb;
+    int nsweeps;
+    int32_t* ctrl;        // G_* words
+    int32_t* prog;        // steps finished, per sweep
+    int64_t watchdog_ticks;
+};
+
+__host__ __device__ inline int64_t nsteps(int64_t n, int nb, int64_t k) {
+    return (n - 1 - k + nb - 1) / nb;
+}
+
+__device__ __forceinline__ double* at(const ChaseArgs& a, int64_t i, int64_t j) {
+    return a.W + (i - j + 2 * a.nb - 1) + j * a.ldw;
+}
+
+__device__ __forceinline__ int aload(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Sum over the workgroup; the result is returned to every thread.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+    x = wave_sum(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w];
+    return s;
+}
+
+// Householder reflector of the L values in v[0 .. L-1] (LDS), in place:
+// v becomes (1, x2 / (alpha - beta)); returns tau (0: the identity) and
+// beta, the value left in the first position.
+__device__ __forceinline__ double reflector(double* v, int L, double* red, double* beta_out) {
+    const int tid = threadIdx.x;
+    const double x = tid < L ? v[tid] : 0.0;
+    const double ss = block_sum(tid >= 1 && tid < L ? x * x : 0.0, red);
+    const double alpha = v[0];
+    __syncthreads();                      // every thread has read v[0] and red
+    if (ss == 0.0) {
+        *beta_out = alpha;
+        return 0.0;
+    }
+    const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+    const double scal = 1.0 / (alpha - beta);
+    if (tid < L) v[tid] = tid == 0 ? 1.0 : x * scal;
+    __syncthreads();
+    *beta_out = beta;
+    return (beta - alpha) / beta;
+}
+
+// Wait until *p >= target (wave 0 polls), then acquire.  false: stop (an
+// error was reported, or the watchdog fired here).
+__device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* flag) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int ok = 1;
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            int v = 0, err = 0;
+            if (lane == 0) {
+                v = aload(p);
+                if (v < target) err = aload(&a.ctrl[G_ERROR]);
+            }
+            v = __builtin_amdgcn_readfirstlane(v);
+            if (v >= target) break;
+            if (__builtin_amdgcn_readfirstlane(err) != 0) {
+                ok = 0;
+                break;
+            }
+            if ((int64_t)(wall_clock64() - t0) > a.watchdog_ticks) {
+                if (lane == 0)
+                    __hip_atomic_store(&a.ctrl[G_ERROR], BB_ETIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (lane == 0) *flag = ok;
+    }
+    __syncthreads();
+    const int ok = __builtin_amdgcn_readfirstlane(*flag);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+// Step t of sweep k.
+__device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, double* red) {
+    const int tid = threadIdx.x;
+    const int nb = a.nb;
+    const int64_t c = k + 1 + t * nb;
+    const int64_t rr = t == 0 ? k : c - nb;
+    const int L = (int)(a.n - c < nb ? a.n - c : nb);
+
+    // right reflector: clear row rr beyond column c
+    if (tid < L) v[tid] = *at(a, rr, c + tid);
+    __syncthreads();
+    double beta;
+    double tau = reflector(v, L, red, &beta);
+    if (tau != 0.0) {
+        if (tid < L) *at(a, rr, c + tid) = tid == 0 ? beta : 0.0;
+        const int R = (int)(c + L - 1 - rr);          // rows rr+1 .. c+L-1
+        for (int r = tid; r < R; r += NT) {
+            const int64_t i = rr + 1 + r;
+            double* p = at(a, i, c);
+            const int64_t step = a.ldw - 1;            // entry (i, j+1) from (i, j)
+            double w = 0.0;
+            for (int j = 0; j < L; ++j) w += p[j * step] * v[j];
+            w *= tau;
+            for (int j = 0; j < L; ++j) p[j * step] -= w * v[j];
+        }
+    }
+    __syncthreads();
+
+    // left reflector: clear column c below the diagonal
+    if (tid < L) v[tid] = *at(a, c + tid, c);
+    __syncthreads();
+    tau = reflector(v, L, red, &beta);
+    if (tau != 0.0) {
+        if (tid < L) *at(a, c + tid, c) = tid == 0 ? beta : 0.0;
+        const int64_t ce = c + 2 * nb < a.n ? c + 2 * nb : a.n;
+        const int C = (int)(ce - c - 1);              // columns c+1 .. ce-1
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int q = wave; q < C; q += NW) {
+            double* p = at(a, c, c + 1 + q);          // rows c .. c+L-1 are contiguous
+            double w = 0.0;
+            for (int i = lane; i < L; i += 64) w += v[i] * p[i];
+            w = tau * wave_sum(w);
+            for (int i = lane; i < L; i += 64) p[i] -= w * v[i];
+        }
+    }
+    __syncthreads();
+}
+
+// The same step with its whole region staged in LDS, for nb <= LDS_NB.  The
+// region is three nb x nb quadrants: U (rows c-nb .. c-1, columns c ..
+// c+nb-1; only rows from rr on are in use), D (rows and columns c ..
+// c+nb-1) and Q (rows c .. c+nb-1, columns c+nb .. c+2nb-1), each stored by
+// column with stride LDS_LD.  In W, U's column q continues into D's column q
+// (rows c-nb .. c+nb-1 are contiguous), so both load as one run.  Every
+// load of the step is issued before the first one is waited for (batches
+// of LDS_BATCH per thread), then both reflectors run in LDS, then the
+// region is stored back.
+constexpr int LDS_NB = 64;
+constexpr int LDS_LD = LDS_NB + 1;
+constexpr int LDS_BATCH = 16;
+
+__device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double* U, double* D, double* Q,
+                               double* v, double* red) {
+    const int tid = threadIdx.x;
+    const int nb = a.nb;
+    const int64_t c = k + 1 + t * nb;
+    const int64_t rr = t == 0 ? k : c - nb;
+    const int L = (int)(a.n - c < nb ? a.n - c : nb);
+    const int64_t nq = a.n - (c + nb);
+    const int Lq = nq <= 0 ? 0 : (int)(nq < nb ? nq : nb);
+    const int u0 = (int)(rr - (c - nb));         // first U row in use: 0, or nb-1 when t = 0
+    const int KU = 2 * nb - 1;
+    const int h = nb + L - u0;                   // rows per U/D column in use (D rows < L exist)
+    const int nud = h * L, nqd = L * Lq;
+    // U/D element x: column q = x / h, row u0 + x % h of the 2nb-row run
+    // (rows < nb are U's, the others D's); Q element x: column x / L, row x % L
+    auto ud_src = [&](int x, int& q, int& r) -> const double* {
+        q = x / h;
+        r = u0 + (x - q * h);
+        return a.W + (KU - nb - q + r) + (c + q) * a.ldw;
+    };
+    auto q_src = [&](int x, int& q, int& r) -> const double* {
+        q = x / L;
+        r = x - q * L;
+        return a.W + (KU - nb - q + r) + (c + nb + q) * a.ldw;
+    };
+    for (int x0 = tid; x0 < nud + nqd; x0 += NT * LDS_BATCH) {
+        double tmp[LDS_BATCH];
+#pragma unroll
+        for (int u = 0; u < LDS_BATCH; ++u) {
+            const int x = x0 + u * NT;
+            int q, r;
+            if (x < nud) tmp[u] = *ud_src(x, q, r);
+            else if (x < nud + nqd) tmp[u] = *q_src(x - nud, q, r);
+        }
+#pragma unroll
+        for (int u = 0; u < LDS_BATCH; ++u) {
+            const int x = x0 + u * NT;
+            int q, r;
+            if (x < nud) {
+                ud_src(x, q, r);
+                if (r < nb) U[r + q * LDS_LD] = tmp[u];
+                else D[(r - nb) + q * LDS_LD] = tmp[u];
+            } else if (x < nud + nqd) {
+                q_src(x - nud, q, r);
+                Q[r + q * LDS_LD] = tmp[u];
+            }
+        }
+    }
+    __syncthreads();
+
+    // right reflector: clear row rr (U row u0) beyond column c
+    if (tid < L) v[tid] = U[u0 + tid * LDS_LD];
+    __syncthreads();
+    double beta;
+    double tau = reflector(v, L, red, &beta);
+    if (tau != 0.0) {
+        if (tid < L) U[u0 + tid * LDS_LD] = tid == 0 ? beta : 0.0;
+        const int ru = nb - 1 - u0;                 // U rows u0+1 .. nb-1, then D rows 0 .. L-1
+        for (int r = tid; r < ru + L; r += NT) {
+            double* p = r < ru ? U + (u0 + 1 + r) : D + (r - ru);
+            double w = 0.0;
+            for (int j = 0; j < L; ++j) w += p[j * LDS_LD] * v[j];
+            w *= tau;
+            for (int j = 0; j < L; ++j) p[j * LDS_LD] -= w * v[j];
+        }
+    }
+    __syncthreads();
+
+    // left reflector: clear column c (D column 0) below the diagonal
+    if (tid < L) v[tid] = D[tid];
+    __syncthreads();
+    tau = reflector(v, L, red, &beta);
+    if (tau != 0.0) {
+        if (tid < L) D[tid] = tid == 0 ? beta : 0.0;
+        for (int q = tid; q < L - 1 + Lq; q += NT) {   // D columns 1 .. L-1, then Q columns 0 .. Lq-1
+            double* p = q < L - 1 ? D + (q + 1) * LDS_LD : Q + (q - (L - 1)) * LDS_LD;
+            double w = 0.0;
+            for (int i = 0; i < L; ++i) w += v[i] * p[i];
+            w *= tau;
+            for (int i = 0; i < L; ++i) p[i] -= w * v[i];
+        }
+    }
+    __syncthreads();
+
+    // store the region back
+    for (int x = tid; x < nud + nqd; x += NT) {
+        int q, r;
+        if (x < nud) {
+            double* dst = const_cast<double*>(ud_src(x, q, r));
+            *dst = r < nb ? U[r + q * LDS_LD] : D[(r - nb) + q * LDS_LD];
+        } else {
+            double* dst = const_cast<double*>(q_src(x - nud, q, r));
+            *dst = Q[r + q * LDS_LD];
+        }
+    }
+}
+
+template <bool TILE>
+__global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
+    __shared__ double v[MAX_NB];
+    __shared__ double red[NW];
+    __shared__ double tile[TILE ? 3 * LDS_NB * LDS_LD : 1];
+    __shared__ int sk, flag;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sk = __hip_atomic_fetch_add(&a.ctrl[G_HEAD], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int64_t k = __builtin_amdgcn_readfirstlane(sk);
+        __syncthreads();
+        if (k >= a.nsweeps) return;
+        const int64_t T = nsteps(a.n, a.nb, k);
+        const int64_t Tp = k > 0 ? nsteps(a.n, a.nb, k - 1) : 0;
+        for (int64_t t = 0; t < T; ++t) {
+            if (k > 0 && !wait_geq(a, &a.prog[k - 1], (int)(t + 3 < Tp ? t + 3 : Tp), &flag)) return;
+            if constexpr (TILE)
+                chase_step_lds(a, k, t, tile, tile + LDS_NB * LDS_LD, tile + 2 * LDS_NB * LDS_LD, v, red);
+            else
+                chase_step(a, k, t, v, red);
+            // release: every wave's stores complete and reach the device scope
+            // before the counter moves
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(&a.prog[k], (int)(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Copy the upper band of B into W (zero elsewhere), clear the control words
+// and the progress counters.
+__global__ void pack_kernel(const double* B, int64_t ldb, int64_t n, int nb, double* W, int64_t ldw,
+                            int32_t* ctrl, int32_t* prog, int nsweeps) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (g < G_WORDS) ctrl[g] = 0;
+    for (int64_t s = g; s < nsweeps; s += stride) prog[s] = 0;
+    const int64_t total = ldw * n;
+    for (int64_t x = g; x < total; x += stride) {
+        const int64_t j = x / ldw;
+        const int64_t i = j + (x - j * ldw) - (2 * nb - 1);
+        W[x] = (i >= 0 && i <= j && j - i <= nb) ? B[i + j * ldb] : 0.0;
+    }
+}
+
+__global__ void extract_kernel(const double* W, int64_t ldw, int64_t n, int nb, double* d, double* e) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    d[i] = W[(2 * nb - 1) + i * ldw];
+    if (i + 1 < n) e[i] = W[(2 * nb - 2) + (i + 1) * ldw];
+}
+
+// Number of singular values of (d, e) below x > 0: the negative pivots of
+// T_GK - x I, less the n eigenvalues -sigma_i that are always below x.
+__device__ __forceinline__ int64_t sturm_below(const double* d, const double* e, int64_t n, double x,
+                                               double pivmin) {
+    double q = -x;                   // the first pivot
+    if (fabs(q) < pivmin) q = -pivmin;
+    int64_t cnt = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double di = d[i];
+        q = -x - (di * di) / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+        if (i + 1 < n) {
+            const double ei = e[i];
+            q = -x - (ei * ei) / q;
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += q < 0.0;
+        }
+    }
+    return cnt - n;
+}
+
+__global__ void bisect_kernel(const double* d, const double* e, int64_t n, double* sigma) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    // Gershgorin bound of T_GK and the pivot floor
+    double amax = 0.0, bound = 0.0, prev = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double di = fabs(d[i]);
+        const double ei = i + 1 < n ? fabs(e[i]) : 0.0;
+        bound = fmax(bound, fmax(prev + di, di + ei));
+        amax = fmax(amax, fmax(di, ei));
+        prev = ei;
+    }
+    const double pivmin = DBL_MIN * fmax(1.0, amax * amax);
+    const int64_t s = n - 1 - j;     // sigma[j] is the s-th smallest (decreasing order)
+    double lo = 0.0, hi = bound * (1.0 + 4.0 * DBL_EPSILON) + pivmin;
+    const double abstol = DBL_EPSILON * bound;
+    for (int it = 0; it < 256; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * hi) || mid <= lo || mid >= hi) break;
+        if (sturm_below(d, e, n, mid, pivmin) <= s) lo = mid;
+        else hi = mid;
+    }
+    sigma[j] = 0.5 * (lo + hi);
+}
+
+inline int64_t ws_prog_off(int64_t n, int nb) { return 256 + (int64_t)3 * nb * n * 8; }
+
+inline int nsweeps_of(int64_t n, int nb) { return nb <= 1 || n <= 2 ? 0 : (int)(n - 2); }
+
+inline size_t ws_bytes(int64_t n, int nb) {
+    return (size_t)(ws_prog_off(n, nb) + ((int64_t)nsweeps_of(n, nb) * 4 + 255) / 256 * 256);
+}
+
+int device_attr(hipDeviceAttribute_t attr, int fallback) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, attr, dev) != hipSuccess) return fallback;
+    return v;
+}
+
+}  // namespace bbg
+
+extern "C" {
+
+int bb_bnd2bd_workspace(int64_t n, int nb, size_t* ws_bytes) {
+    if (n < 0) return -1;
+    if (nb < 1 || nb > bbg::MAX_NB) return -2;
+    if (!ws_bytes) return -3;
+    *ws_bytes = bbg::ws_bytes(n, nb);
+    return BB_OK;
+}
+
+int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
+              size_t ws_bytes, double watchdog_s, void* stream) {
+    if (n < 0) return -3;
+    if (!B && n > 0) return -1;
+    if (ldb < (n > 1 ? n : 1)) return -2;
+    if (nb < 1 || nb > bbg::MAX_NB) return -4;
+    if (!d && n > 0) return -5;
+    if (!e && n > 1) return -6;
+    if (!ws && n > 0) return -7;
+    if (ws_bytes < bbg::ws_bytes(n, nb)) return BB_EWORKSPACE;
+    if (n == 0) return BB_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int nsw = bbg::nsweeps_of(n, nb);
+    bbg::ChaseArgs a;
+    a.W = (double*)((char*)ws + 256);
+    a.ldw = 3 * (int64_t)nb;
+    a.n = n;
+    a.nb = nb;
+    a.nsweeps = nsw;
+    a.ctrl = (int32_t*)ws;
+    a.prog = (int32_t*)((char*)ws + bbg::ws_prog_off(n, nb));
+    const double khz = (double)bbg::device_attr(hipDeviceAttributeWallClockRate, 100000);
+    a.watchdog_ticks = (int64_t)((watchdog_s > 0 ? watchdog_s : 30.0) * khz * 1000.0);
+    const int cus = bbg::device_attr(hipDeviceAttributeMultiprocessorCount, 256);
+    const int64_t total = a.ldw * n;
+    int blocks = (int)std::min<int64_t>((total + 255) / 256, 8 * (int64_t)cus);
+    hipLaunchKernelGGL(bbg::pack_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, B, ldb, n, nb, a.W,
+                       a.ldw, a.ctrl, a.prog, nsw);
+    if (hipGetLastError() != hipSuccess) return BB_EHIP;
+    if (nsw > 0) {
+        const int grid = std::min(nsw, cus);
+        if (nb <= bbg::LDS_NB)
+            hipLaunchKernelGGL(bbg::chase_kernel<true>, dim3(grid), dim3(bbg::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL(bbg::chase_kernel<false>, dim3(grid), dim3(bbg::NT), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return BB_EHIP;
+    }
+    hipLaunchKernelGGL(bbg::extract_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.W, a.ldw, n,
+                       nb, d, e);
+    return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
+}
+
+int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* stream) {
+    if (n < 0) return -3;
+    if (!d && n > 0) return -1;
+    if (!e && n > 1) return -2;
+    if (!sigma && n > 0) return -4;
+    if (n == 0) return BB_OK;
+    hipLaunchKernelGGL(bbg::bisect_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, (hipStream_t)stream, d,
+                       e, n, sigma);
+    return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
+}
+
+}  // extern "C"
