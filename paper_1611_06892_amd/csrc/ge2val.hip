@@ -150,13 +150,25 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
     return ok != 0;
 }
 
-// Step t of sweep k.
-__device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, double* red) {
+// Step t of sweep k for nb > LDS_NB, on the band array in global memory.
+// Both updates are rank-one: the right one, M -= tau (M v) v^T on rows
+// rr+1 .. c+L-1 of columns c .. c+L-1, runs one row per thread in two passes
+// (the row products, then the update); the left one, M -= tau v (v^T M) on
+// rows c .. c+L-1 of columns c+1 .. ce-1, runs one row per thread on chunks
+// of CHUNK columns, whose column sums are formed through LDS, so each entry
+// is read and written once.  In the band array entry (i, j+1) follows entry
+// (i, j) at a distance of ldw - 1.
+constexpr int CHUNK = 32;
+constexpr int PLD = NT + 8;              // LDS stride of a product column: lanes 8u+s hit distinct banks
+
+__device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, double* red, double* P,
+                           double* wq) {
     const int tid = threadIdx.x;
     const int nb = a.nb;
     const int64_t c = k + 1 + t * nb;
     const int64_t rr = t == 0 ? k : c - nb;
     const int L = (int)(a.n - c < nb ? a.n - c : nb);
+    const int64_t s = a.ldw - 1;
 
     // right reflector: clear row rr beyond column c
     if (tid < L) v[tid] = *at(a, rr, c + tid);
@@ -167,13 +179,30 @@ __device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, 
         if (tid < L) *at(a, rr, c + tid) = tid == 0 ? beta : 0.0;
         const int R = (int)(c + L - 1 - rr);          // rows rr+1 .. c+L-1
         for (int r = tid; r < R; r += NT) {
-            const int64_t i = rr + 1 + r;
-            double* p = at(a, i, c);
-            const int64_t step = a.ldw - 1;            // entry (i, j+1) from (i, j)
-            double w = 0.0;
-            for (int j = 0; j < L; ++j) w += p[j * step] * v[j];
-            w *= tau;
-            for (int j = 0; j < L; ++j) p[j * step] -= w * v[j];
+            double* p = at(a, rr + 1 + r, c);
+            double w0 = 0.0, w1 = 0.0;
+            int j = 0;
+            for (; j + 16 <= L; j += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = p[(j + u) * s];
+#pragma unroll
+                for (int u = 0; u < 16; u += 2) {
+                    w0 += x[u] * v[j + u];
+                    w1 += x[u + 1] * v[j + u + 1];
+                }
+            }
+            for (; j < L; ++j) w0 += p[j * s] * v[j];
+            const double w = tau * (w0 + w1);
+            j = 0;
+            for (; j + 16 <= L; j += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = p[(j + u) * s];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) p[(j + u) * s] = x[u] - w * v[j + u];
+            }
+            for (; j < L; ++j) p[j * s] -= w * v[j];
         }
     }
     __syncthreads();
@@ -186,124 +215,189 @@ __device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, 
         if (tid < L) *at(a, c + tid, c) = tid == 0 ? beta : 0.0;
         const int64_t ce = c + 2 * nb < a.n ? c + 2 * nb : a.n;
         const int C = (int)(ce - c - 1);              // columns c+1 .. ce-1
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int q = wave; q < C; q += NW) {
-            double* p = at(a, c, c + 1 + q);          // rows c .. c+L-1 are contiguous
-            double w = 0.0;
-            for (int i = lane; i < L; i += 64) w += v[i] * p[i];
-            w = tau * wave_sum(w);
-            for (int i = lane; i < L; i += 64) p[i] -= w * v[i];
+        const double vi = tid < L ? v[tid] : 0.0;
+        double* p = tid < L ? at(a, c + tid, c + 1) : nullptr;
+        const int cu = tid >> 3, cs = tid & 7;        // column sums: column cu, rows cs + 8 r
+        for (int q0 = 0; q0 < C; q0 += CHUNK) {
+            double x[CHUNK];
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? p[(q0 + u) * s] : 0.0;
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) P[u * PLD + tid] = vi * x[u];
+            __syncthreads();
+            double sum = 0.0;
+            for (int r = cs; r < L; r += 8) sum += P[cu * PLD + r];
+            sum += __shfl_xor(sum, 1, 64);
+            sum += __shfl_xor(sum, 2, 64);
+            sum += __shfl_xor(sum, 4, 64);
+            if (cs == 0) wq[cu] = tau * sum;
+            __syncthreads();
+            if (tid < L) {
+#pragma unroll
+                for (int u = 0; u < CHUNK; ++u)
+                    if (q0 + u < C) p[(q0 + u) * s] = x[u] - vi * wq[u];
+            }
         }
     }
     __syncthreads();
 }
 
-// The same step with its whole region staged in LDS, for nb <= LDS_NB.  The
-// region is three nb x nb quadrants: U (rows c-nb .. c-1, columns c ..
-// c+nb-1; only rows from rr on are in use), D (rows and columns c ..
-// c+nb-1) and Q (rows c .. c+nb-1, columns c+nb .. c+2nb-1), each stored by
-// column with stride LDS_LD.  In W, U's column q continues into D's column q
-// (rows c-nb .. c+nb-1 are contiguous), so both load as one run.  Every
-// load of the step is issued before the first one is waited for (batches
-// of LDS_BATCH per thread), then both reflectors run in LDS, then the
-// region is stored back.
+// Reflector of the L <= 64 values x[i ld] (LDS), formed by wave 0 alone: v
+// gets (1, x2 / (alpha - beta)), x gets (beta, 0, ..), sc[0] tau (0: the
+// identity, x left as it is).  The caller synchronizes after it.
+__device__ __forceinline__ void reflector_wave(double* x, int ld, int L, double* v, double* sc) {
+    const int lane = threadIdx.x;
+    const double xi = lane < L ? x[lane * ld] : 0.0;
+    const double ss = wave_sum(lane >= 1 ? xi * xi : 0.0);
+    const double alpha = __shfl(xi, 0, 64);
+    double tau = 0.0;
+    if (ss != 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        const double scal = 1.0 / (alpha - beta);
+        tau = (beta - alpha) / beta;
+        if (lane < L) {
+            v[lane] = lane == 0 ? 1.0 : xi * scal;
+            x[lane * ld] = lane == 0 ? beta : 0.0;
+        }
+    }
+    if (lane == 0) sc[0] = tau;
+}
+
+// The same step with its region staged in LDS, for nb <= LDS_NB.  The region
+// is three nb x nb quadrants, each stored by column with stride LDS_LD: U
+// (rows c-nb .. c-1 of columns c .. c+nb-1; only rows from rr on are in
+// use), D (rows and columns c .. c+nb-1) and Q (rows c .. c+nb-1, columns
+// c+nb .. c+2nb-1).  Q of step t is U of step t+1, and no other sweep
+// touches it between the two (the sweep ahead finished its steps there
+// before step t started, the sweep behind waits for step t+1), so it stays
+// in LDS: the three buffers rotate, step t loads only D and Q (and, for
+// t = 0, the row k), and stores U and D; Q reaches memory as the next
+// step's U (the last step of a sweep has no Q).  Thread tid moves row
+// tid % nb of columns tid / nb + j (NT / nb), all its loads issued before
+// the first is used.  With the band array's column stride ldw and the
+// entry (i, j+1) at ldw - 1 after (i, j), for d0 = W + 2nb - 1 + c ldw:
+//     D(r, q) = d0 + r + q (ldw - 1),  U(r, q) = D(r, q) - nb,
+//     Q(r, q) = D(r, q) - nb + nb ldw.
 constexpr int LDS_NB = 64;
 constexpr int LDS_LD = LDS_NB + 1;
-constexpr int LDS_BATCH = 16;
+// columns a thread moves, at most: cpp = NT / nb >= NT / LDS_NB, so LDS_J cpp >= nb
+constexpr int LDS_J = (LDS_NB + NT / LDS_NB - 1) / (NT / LDS_NB);
+static_assert(LDS_J <= 16, "per-thread staging registers");
+// the updates give each row (column) of a quadrant pair two lanes, each with
+// half of it in registers: 2 (2 nb - 1) <= NT lanes
+constexpr int HALF = LDS_NB / 2;
+static_assert(2 * (2 * LDS_NB - 1) <= NT, "one pass of lane pairs");
 
 __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double* U, double* D, double* Q,
-                               double* v, double* red) {
+                               double* v, double* sc) {
     const int tid = threadIdx.x;
     const int nb = a.nb;
     const int64_t c = k + 1 + t * nb;
-    const int64_t rr = t == 0 ? k : c - nb;
     const int L = (int)(a.n - c < nb ? a.n - c : nb);
     const int64_t nq = a.n - (c + nb);
     const int Lq = nq <= 0 ? 0 : (int)(nq < nb ? nq : nb);
-    const int u0 = (int)(rr - (c - nb));         // first U row in use: 0, or nb-1 when t = 0
-    const int KU = 2 * nb - 1;
-    const int h = nb + L - u0;                   // rows per U/D column in use (D rows < L exist)
-    const int nud = h * L, nqd = L * Lq;
-    // U/D element x: column q = x / h, row u0 + x % h of the 2nb-row run
-    // (rows < nb are U's, the others D's); Q element x: column x / L, row x % L
-    auto ud_src = [&](int x, int& q, int& r) -> const double* {
-        q = x / h;
-        r = u0 + (x - q * h);
-        return a.W + (KU - nb - q + r) + (c + q) * a.ldw;
-    };
-    auto q_src = [&](int x, int& q, int& r) -> const double* {
-        q = x / L;
-        r = x - q * L;
-        return a.W + (KU - nb - q + r) + (c + nb + q) * a.ldw;
-    };
-    for (int x0 = tid; x0 < nud + nqd; x0 += NT * LDS_BATCH) {
-        double tmp[LDS_BATCH];
+    const int u0 = t == 0 ? nb - 1 : 0;          // first U row in use
+    const int64_t s = a.ldw - 1;
+    const int cpp = NT / nb;                     // columns moved at once
+    const int tr = tid % nb, tq = tid / nb;
+    const bool mover = tq < cpp && tr < L;       // D and Q rows < L exist
+    const double* db = a.W + (2 * nb - 1) + c * a.ldw;
+    const double* d0 = db + tr;
+    const double* q0p = d0 - nb + (int64_t)nb * a.ldw;
+    {
+        double xd[LDS_J], xq[LDS_J];
+        const double xu = t == 0 && tid < L ? db[tid * s - 1] : 0.0;     // U(nb-1, tid): the row k
 #pragma unroll
-        for (int u = 0; u < LDS_BATCH; ++u) {
-            const int x = x0 + u * NT;
-            int q, r;
-            if (x < nud) tmp[u] = *ud_src(x, q, r);
-            else if (x < nud + nqd) tmp[u] = *q_src(x - nud, q, r);
+        for (int j = 0; j < LDS_J; ++j) {
+            const int q = tq + j * cpp;
+            xd[j] = mover && q < L ? d0[q * s] : 0.0;
+            xq[j] = mover && q < Lq ? q0p[q * s] : 0.0;
+        }
+        if (t == 0 && tid < L) U[(nb - 1) + tid * LDS_LD] = xu;
+#pragma unroll
+        for (int j = 0; j < LDS_J; ++j) {
+            const int q = tq + j * cpp;
+            if (mover && q < L) D[tr + q * LDS_LD] = xd[j];
+            if (mover && q < Lq) Q[tr + q * LDS_LD] = xq[j];
+        }
+    }
+    __syncthreads();
+
+    // right reflector (wave 0): clear row rr (U row u0) beyond column c;
+    // then rows U u0+1 .. nb-1 and D 0 .. L-1 take M -= tau (M v) v^T
+    if (tid < 64) reflector_wave(U + u0, LDS_LD, L, v, sc);
+    __syncthreads();
+    const int pr = tid >> 1, ph = tid & 1;       // a pair of lanes per row (column): halves of it
+    double tau = sc[0];
+    if (tau != 0.0) {
+        const int ru = nb - 1 - u0;
+        const bool act = pr < ru + L;
+        double* p = pr < ru ? U + (u0 + 1 + pr) : D + (pr - ru);
+        double x[HALF];
+        double w = 0.0;
+#pragma unroll
+        for (int u = 0; u < HALF; ++u) {
+            const int j = ph * HALF + u;
+            x[u] = act && j < L ? p[j * LDS_LD] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < LDS_BATCH; ++u) {
-            const int x = x0 + u * NT;
-            int q, r;
-            if (x < nud) {
-                ud_src(x, q, r);
-                if (r < nb) U[r + q * LDS_LD] = tmp[u];
-                else D[(r - nb) + q * LDS_LD] = tmp[u];
-            } else if (x < nud + nqd) {
-                q_src(x - nud, q, r);
-                Q[r + q * LDS_LD] = tmp[u];
-            }
+        for (int u = 0; u < HALF; ++u) {
+            const int j = ph * HALF + u;
+            if (j < L) w += x[u] * v[j];
+        }
+        w = tau * (w + __shfl_xor(w, 1, 64));
+#pragma unroll
+        for (int u = 0; u < HALF; ++u) {
+            const int j = ph * HALF + u;
+            if (act && j < L) p[j * LDS_LD] = x[u] - w * v[j];
         }
     }
     __syncthreads();
 
-    // right reflector: clear row rr (U row u0) beyond column c
-    if (tid < L) v[tid] = U[u0 + tid * LDS_LD];
+    // left reflector (wave 0): clear column c (D column 0) below the
+    // diagonal; then D columns 1 .. L-1 and Q columns 0 .. Lq-1 take
+    // M -= tau v (v^T M)
+    if (tid < 64) reflector_wave(D, 1, L, v, sc);
     __syncthreads();
-    double beta;
-    double tau = reflector(v, L, red, &beta);
+    tau = sc[0];
     if (tau != 0.0) {
-        if (tid < L) U[u0 + tid * LDS_LD] = tid == 0 ? beta : 0.0;
-        const int ru = nb - 1 - u0;                 // U rows u0+1 .. nb-1, then D rows 0 .. L-1
-        for (int r = tid; r < ru + L; r += NT) {
-            double* p = r < ru ? U + (u0 + 1 + r) : D + (r - ru);
-            double w = 0.0;
-            for (int j = 0; j < L; ++j) w += p[j * LDS_LD] * v[j];
-            w *= tau;
-            for (int j = 0; j < L; ++j) p[j * LDS_LD] -= w * v[j];
+        const bool act = pr < L - 1 + Lq;
+        double* p = pr < L - 1 ? D + (pr + 1) * LDS_LD : Q + (pr - (L - 1)) * LDS_LD;
+        double x[HALF];
+        double w = 0.0;
+#pragma unroll
+        for (int u = 0; u < HALF; ++u) {
+            const int i = ph * HALF + u;
+            x[u] = act && i < L ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < HALF; ++u) {
+            const int i = ph * HALF + u;
+            if (i < L) w += v[i] * x[u];
+        }
+        w = tau * (w + __shfl_xor(w, 1, 64));
+#pragma unroll
+        for (int u = 0; u < HALF; ++u) {
+            const int i = ph * HALF + u;
+            if (act && i < L) p[i] = x[u] - w * v[i];
         }
     }
     __syncthreads();
 
-    // left reflector: clear column c (D column 0) below the diagonal
-    if (tid < L) v[tid] = D[tid];
-    __syncthreads();
-    tau = reflector(v, L, red, &beta);
-    if (tau != 0.0) {
-        if (tid < L) D[tid] = tid == 0 ? beta : 0.0;
-        for (int q = tid; q < L - 1 + Lq; q += NT) {   // D columns 1 .. L-1, then Q columns 0 .. Lq-1
-            double* p = q < L - 1 ? D + (q + 1) * LDS_LD : Q + (q - (L - 1)) * LDS_LD;
-            double w = 0.0;
-            for (int i = 0; i < L; ++i) w += v[i] * p[i];
-            w *= tau;
-            for (int i = 0; i < L; ++i) p[i] -= w * v[i];
+    // store U (rows u0 .. nb-1) and D back; Q stays for the next step
+    double* ud = const_cast<double*>(d0);
+    if (tq < cpp && tr >= u0) {
+#pragma unroll
+        for (int j = 0; j < LDS_J; ++j) {
+            const int q = tq + j * cpp;
+            if (q < L) ud[q * s - nb] = U[tr + q * LDS_LD];
         }
     }
-    __syncthreads();
-
-    // store the region back
-    for (int x = tid; x < nud + nqd; x += NT) {
-        int q, r;
-        if (x < nud) {
-            double* dst = const_cast<double*>(ud_src(x, q, r));
-            *dst = r < nb ? U[r + q * LDS_LD] : D[(r - nb) + q * LDS_LD];
-        } else {
-            double* dst = const_cast<double*>(q_src(x - nud, q, r));
-            *dst = Q[r + q * LDS_LD];
+    if (mover) {
+#pragma unroll
+        for (int j = 0; j < LDS_J; ++j) {
+            const int q = tq + j * cpp;
+            if (q < L) ud[q * s] = D[tr + q * LDS_LD];
         }
     }
 }
@@ -312,7 +406,9 @@ template <bool TILE>
 __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
     __shared__ double v[MAX_NB];
     __shared__ double red[NW];
-    __shared__ double tile[TILE ? 3 * LDS_NB * LDS_LD : 1];
+    // TILE: the three rotating quadrant buffers; else the left update's
+    // column products and sums
+    __shared__ double lds[TILE ? 3 * LDS_NB * LDS_LD : CHUNK * PLD + CHUNK];
     __shared__ int sk, flag;
     const int tid = threadIdx.x;
     for (;;) {
@@ -325,10 +421,15 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
         const int64_t Tp = k > 0 ? nsteps(a.n, a.nb, k - 1) : 0;
         for (int64_t t = 0; t < T; ++t) {
             if (k > 0 && !wait_geq(a, &a.prog[k - 1], (int)(t + 3 < Tp ? t + 3 : Tp), &flag)) return;
-            if constexpr (TILE)
-                chase_step_lds(a, k, t, tile, tile + LDS_NB * LDS_LD, tile + 2 * LDS_NB * LDS_LD, v, red);
-            else
-                chase_step(a, k, t, v, red);
+            if constexpr (TILE) {
+                const int u = (int)((2 * t) % 3);    // Q of step t is U of step t+1
+                double* U = lds + u * LDS_NB * LDS_LD;
+                double* D = lds + ((u + 1) % 3) * LDS_NB * LDS_LD;
+                double* Q = lds + ((u + 2) % 3) * LDS_NB * LDS_LD;
+                chase_step_lds(a, k, t, U, D, Q, v, red);   // red[0]: tau
+            } else {
+                chase_step(a, k, t, v, red, lds, lds + CHUNK * PLD);
+            }
             // release: every wave's stores complete and reach the device scope
             // before the counter moves
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
