@@ -9,8 +9,10 @@ timed region).  GFLOP/s uses the paper's operation count 4 n^2 (m - n/3)
 (Section 6.2).  The line also carries the roofline of the persistent kernel
 (HIP events on its launch stream), the FP64 oracle timed on host cores on a
 bounded sample of the same recipe (all cores and one thread), and extra keys
-for the other workloads: the tall graded 32768 x 2048 reduction, the batch of
-4096 matrices, the adjoint of the 8192 x 1024 reduction, the same square at
+for the other workloads: the singular values of the square input through the
+band (GE2VAL: bulge chase and bisection after the reduction, at the headline
+nb and at nb = 64), the tall graded 32768 x 2048 reduction, the batch of 4096
+matrices, the adjoint of the 8192 x 1024 reduction, the same square at
 nb = 128 and its FP32-update form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
@@ -147,8 +149,60 @@ def gaussian_input(torch, m, n, seed):
     return torch.randn(m, n, generator=gen, device="cuda", dtype=torch.float64)
 
 
+def chase_bytes(n, nb):
+    """Algorithmic bytes of the bulge chase: every step reads and writes once
+    the entries its two reflectors change (the cleared row's block, the
+    rows between it and the diagonal block, the diagonal block and the block
+    right of it), 16 bytes an entry."""
+    total = 0
+    for k in range(max(n - 2, 0) if nb > 1 else 0):
+        c = k + 1
+        first = True
+        while c < n:
+            L = min(nb, n - c)
+            Lq = max(min(nb, n - c - nb), 0)
+            rows_above = 1 if first else nb            # rows rr .. c-1
+            total += (rows_above * L + L * L + L * Lq) * 16
+            c += nb
+            first = False
+    return total
+
+
+def ge2val_stage(bb, torch, np, S, m, n, nb, s_ref, e2bnd_ms):
+    """BND2BD + BD2VAL on the band a reduction left in S (column-major, leading
+    dimension m), timed with HIP events on the launch stream; singular values
+    checked against the prescribed ones."""
+    warm = torch.zeros(300, 300, dtype=torch.float64, device="cuda")
+    bb.bd2val(*bb.bnd2bd(warm, 300, 300, min(nb, 299)))           # code objects loaded before timing
+    ws = torch.empty(bb.bnd2bd_workspace(n, nb), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    d, e = bb.bnd2bd(S, m, n, nb, ws=ws, watchdog_s=60.0, check=False)
+    ev[1].record()
+    sig = bb.bd2val(d, e)
+    ev[2].record()
+    torch.cuda.synchronize()
+    st = bb.poll_error(ws)
+    if st != 0:
+        raise RuntimeError("bulge chase error %d" % st)
+    chase_ms = ev[0].elapsed_time(ev[1])
+    bd_ms = ev[1].elapsed_time(ev[2])
+    ref = np.sort(np.asarray(s_ref))[::-1]
+    err = float(np.max(np.abs(sig.cpu().numpy() - ref))) / float(ref[0])
+    nbytes = chase_bytes(n, nb)
+    gbs = nbytes / (chase_ms * 1e-3) / 1e9
+    return {"nb": nb, "ge2bnd_ms": round(e2bnd_ms, 3), "bnd2bd_ms": round(chase_ms, 3),
+            "bd2val_ms": round(bd_ms, 3), "total_ms": round(e2bnd_ms + chase_ms + bd_ms, 3),
+            "sigma_max_rel_err": err, "tol": 50 * n * np.finfo(np.float64).eps,
+            "bnd2bd_roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": 8000.0, "unit": "GB/s",
+                                "frac": round(gbs / 8000.0, 5), "traffic": None,
+                                "kernel": "chase_kernel<%s>" % ("true" if nb <= 64 else "false"),
+                                "algorithmic_bytes": nbytes}}
+
+
 def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, steps=None,
-                 warmup=None, probes=True, label="square"):
+                 warmup=None, probes=True, label="square", ge2val=False):
     """The graded m x n square workload (default 16384^2): reduction timing,
     band check, ||B||_F against ||s||, probe vectors through Q and P."""
     cfg = workloads.CONFIGS["square_graded"]
@@ -189,8 +243,26 @@ def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, 
         plan.apply_q(Zs, m, 8, vt)
         torch.cuda.synchronize()
         probe = float(torch.linalg.norm(Y1 - Zs.t())) / (nA * float(torch.linalg.norm(X)))
-    del Ad, S0, S, B
     kern_ms = float(np.mean(kms))
+    g2v = None
+    if ge2val and s is not None:
+        log("GE2VAL: band to bidiagonal and singular values at nb=%d" % nb)
+        g2v = [ge2val_stage(bb, torch, np, S, m, n, nb, s, kern_ms)]
+        del S, B, vt
+        nb2 = 64
+        plan2 = bb.Plan(m, n, nb2, "auto", variant, sched=args.sched, timing=True, watchdog_s=60.0)
+        vt2, ws2 = plan2.alloc()
+        S2 = S0.clone()
+        plan2.execute(S2, m, vt2, ws2)
+        torch.cuda.synchronize()
+        if bb.poll_error(ws2) != 0:
+            raise RuntimeError("device scheduler error %d" % bb.poll_error(ws2))
+        log("GE2VAL: the same input reduced at nb=%d: %.2f ms" % (nb2, plan2.last_kernel_ms()))
+        g2v.append(ge2val_stage(bb, torch, np, S2, m, n, nb2, s, plan2.last_kernel_ms()))
+        del S2, vt2, ws2
+    else:
+        del S, B
+    del Ad, S0
     flops = workloads.flops_bidiag(m, n)
     algo = workloads.flops_rbidiag_actual(m, n) if variant == "rbidiag" else flops
     peak = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
@@ -205,6 +277,7 @@ def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, 
                      "kernel_ms": round(kern_ms, 3), "algorithmic_flops": algo},
         "check": {"band_exact": band_ok, "fro_norm_rel_err": fro, "probe_rel_err": probe,
                   "tol": 50 * n * np.finfo(np.float64).eps},
+        "ge2val": g2v,
     }
 
 
@@ -320,7 +393,7 @@ def main():
     ap.add_argument("--nb", type=int, default=0, help="tile size (0: the workload's)")
     ap.add_argument("--m", type=int, default=0, help="rows (0: the workload's)")
     ap.add_argument("--n", type=int, default=0, help="columns (0: the workload's)")
-    ap.add_argument("--extras", default="tall,batch,adjoint,nb128,f32",
+    ap.add_argument("--extras", default="ge2val,tall,batch,adjoint,nb128,f32",
                     help="comma list of extra workloads (empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--input", default="graded", choices=["graded", "gaussian"],
@@ -339,9 +412,14 @@ def main():
     import paper_1611_06892_amd as bb
     import workloads
 
-    head = bench_square(args, bb, torch, np, workloads)
-    extras = {}
     wanted = [e for e in args.extras.split(",") if e]
+    head = bench_square(args, bb, torch, np, workloads, ge2val="ge2val" in wanted)
+    extras = {}
+    if head["ge2val"]:
+        extras["ge2val"] = {"workload": "GE2BND + BND2BD + BD2VAL of the square graded %dx%d input, "
+                                        "the headline band and one reduced at nb=64 (auto tree)"
+                                        % (head["m"], head["n"]),
+                            "runs": head["ge2val"]}
     if "nb128" in wanted:
         r = bench_square(args, bb, torch, np, workloads, nb=128, tree="greedy", prec="f64", steps=3,
                          warmup=1, probes=False, label="square nb128")
