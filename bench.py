@@ -11,7 +11,7 @@ timed region).  GFLOP/s uses the paper's operation count 4 n^2 (m - n/3)
 bounded sample of the same recipe (all cores and one thread), and extra keys
 for the other workloads: the singular values of the square input through the
 band (GE2VAL: bulge chase and bisection after the reduction, at the headline
-nb and at nb = 64), the tall graded 32768 x 2048 reduction, the batch of 4096
+nb and at nb = 128), the tall graded 32768 x 2048 reduction, the batch of 4096
 matrices, the adjoint of the 8192 x 1024 reduction, the same square at
 nb = 128 and its FP32-update form.
 
@@ -249,8 +249,8 @@ def bench_square(args, bb, torch, np, workloads, nb=None, tree=None, prec=None, 
         log("GE2VAL: band to bidiagonal and singular values at nb=%d" % nb)
         g2v = [ge2val_stage(bb, torch, np, S, m, n, nb, s, kern_ms)]
         del S, B, vt
-        nb2 = 64
-        plan2 = bb.Plan(m, n, nb2, "auto", variant, sched=args.sched, timing=True, watchdog_s=60.0)
+        nb2 = 128
+        plan2 = bb.Plan(m, n, nb2, "greedy", variant, sched=args.sched, timing=True, watchdog_s=60.0)
         vt2, ws2 = plan2.alloc()
         S2 = S0.clone()
         plan2.execute(S2, m, vt2, ws2)
@@ -417,7 +417,7 @@ def main():
     extras = {}
     if head["ge2val"]:
         extras["ge2val"] = {"workload": "GE2BND + BND2BD + BD2VAL of the square graded %dx%d input, "
-                                        "the headline band and one reduced at nb=64 (auto tree)"
+                                        "the headline band and one reduced at nb=128 (greedy tree)"
                                         % (head["m"], head["n"]),
                             "runs": head["ge2val"]}
     if "nb128" in wanted:

@@ -438,13 +438,14 @@ int bb_choose(int64_t m, int64_t n, int nb, const bb_opts* opts, int* tree, int*
  * only entries with 0 <= j - i <= nb are read, B is not written) to upper
  * bidiagonal form U^T B V (U, V orthogonal, V e1 = e1, neither formed) by
  * two-sided Householder bulge chasing, one row per sweep, the sweeps
- * pipelined over the GPU in one persistent launch.  Writes the diagonal
+ * pipelined over the GPU in one persistent launch (for nb > 128 each sweep
+ * is run by a group of workgroups).  Writes the diagonal
  * d[0..n-1] and the superdiagonal e[0..n-2] (device).  The diagonal and
  * superdiagonal are those of the Golub-Kahan bidiagonalization of B started
  * at e1, so they are unique up to signs.
  * ws: device workspace of bb_bnd2bd_workspace bytes (control words, the band
- * with room for the fill, 24 nb n bytes, and one progress counter per
- * sweep), overwritten.  watchdog_s: seconds a sweep may wait for the one
+ * with room for the fill, 24 nb n bytes, and a progress counter and a
+ * group-barrier counter per sweep), overwritten.  watchdog_s: seconds a sweep may wait for the one
  * before it (0 = 30); when it fires the launch stops and bb_poll_error(ws)
  * reports BB_ETIMEOUT.  Arguments: B (1), ldb >= max(1, n) (2), n >= 0 (3),
  * 1 <= nb <= 256 (4), d (5), e (6), ws (7), ws_bytes (8, BB_EWORKSPACE when

@@ -61,6 +61,8 @@ struct ChaseArgs {
     int nsweeps;
     int32_t* ctrl;        // G_* words
     int32_t* prog;        // steps finished, per sweep
+    int32_t* bar;         // group barrier arrivals, per sweep (nb > LDS_NB)
+    int group;            // workgroups per sweep (nb > LDS_NB; 1 for the LDS steps)
     int64_t watchdog_ticks;
 };
 
@@ -150,21 +152,41 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
     return ok != 0;
 }
 
-// Step t of sweep k for nb > LDS_NB, on the band array in global memory.
-// Both updates are rank-one: the right one, M -= tau (M v) v^T on rows
-// rr+1 .. c+L-1 of columns c .. c+L-1, runs one row per thread in two passes
-// (the row products, then the update); the left one, M -= tau v (v^T M) on
-// rows c .. c+L-1 of columns c+1 .. ce-1, runs one row per thread on chunks
-// of CHUNK columns, whose column sums are formed through LDS, so each entry
-// is read and written once.  In the band array entry (i, j+1) follows entry
-// (i, j) at a distance of ldw - 1.
+// Step t of sweep k for nb > LDS_NB, on the band array in global memory, by
+// member g of the group of a.group workgroups that runs the sweep.  Only
+// n / (3 nb) sweeps can run at once (21 at n = 16384, nb = 256), so each
+// sweep's steps are spread over a group to use the other CUs.
+//   * Every member reads row rr and forms the right reflector (the same
+//     arithmetic, the same result); the right update M -= tau (M v) v^T of
+//     rows rr+1 .. c+L-1 of columns c .. c+L-1 is split by rows, TPR lanes a
+//     row, in two passes (the row products, then the update).
+//   * Group barrier: column c is final.
+//   * Every member reads column c and forms the left reflector; the left
+//     update M -= tau v (v^T M) of rows c .. c+L-1 of columns c+1 .. ce-1 is
+//     split by chunks of CHUNK columns, one row per thread, the column sums
+//     formed through LDS, each entry read and written once.
+//   * Group barrier: the step's updates are done.  Member 0 then writes the
+//     cleared row rr and column c (beta, zeros), which no member reads later
+//     in the step or in the next one, and publishes the step.
+// In the band array entry (i, j+1) follows entry (i, j) at a distance of
+// ldw - 1.  false: an error was reported or the watchdog fired.
+constexpr int GROUP_NB = 128;
+constexpr int GROUP_MAX = 6;
 constexpr int CHUNK = 32;
 constexpr int PLD = NT + 8;              // LDS stride of a product column: lanes 8u+s hit distinct banks
 
-__device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, double* red, double* P,
-                           double* wq) {
+__device__ bool group_barrier(const ChaseArgs& a, int64_t k, int target, int* flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");          // in every wave
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.bar[k], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return wait_geq(a, &a.bar[k], target, flag);
+}
+
+__device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, double* v, double* red, double* P,
+                           double* wq, int* flag) {
     const int tid = threadIdx.x;
     const int nb = a.nb;
+    const int G = a.group;
     const int64_t c = k + 1 + t * nb;
     const int64_t rr = t == 0 ? k : c - nb;
     const int L = (int)(a.n - c < nb ? a.n - c : nb);
@@ -173,52 +195,60 @@ __device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, 
     // right reflector: clear row rr beyond column c
     if (tid < L) v[tid] = *at(a, rr, c + tid);
     __syncthreads();
-    double beta;
-    double tau = reflector(v, L, red, &beta);
-    if (tau != 0.0) {
-        if (tid < L) *at(a, rr, c + tid) = tid == 0 ? beta : 0.0;
+    double beta_r, beta_l;
+    const double tau_r = reflector(v, L, red, &beta_r);
+    if (tau_r != 0.0) {
         const int R = (int)(c + L - 1 - rr);          // rows rr+1 .. c+L-1
-        for (int r = tid; r < R; r += NT) {
+        const int rpm = (R + G - 1) / G;              // rows of this member: r0 .. r1-1
+        const int r0 = g * rpm, r1 = r0 + rpm < R ? r0 + rpm : R;
+        int tpr = 1;                                  // lanes a row: a power of two <= 8
+        while (tpr < 8 && 2 * tpr * rpm <= NT) tpr *= 2;
+        const int part = tid & (tpr - 1);
+        // the tpr lanes of a row are adjacent and share its loop trips, so
+        // the shuffles that sum their parts stay within active lanes
+        for (int r = r0 + tid / tpr; r < r1; r += NT / tpr) {
             double* p = at(a, rr + 1 + r, c);
             double w0 = 0.0, w1 = 0.0;
-            int j = 0;
-            for (; j + 16 <= L; j += 16) {
+            int j = part;
+            for (; j + 15 * tpr < L; j += 16 * tpr) {
                 double x[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = p[(j + u) * s];
+                for (int u = 0; u < 16; ++u) x[u] = p[(j + u * tpr) * s];
 #pragma unroll
                 for (int u = 0; u < 16; u += 2) {
-                    w0 += x[u] * v[j + u];
-                    w1 += x[u + 1] * v[j + u + 1];
+                    w0 += x[u] * v[j + u * tpr];
+                    w1 += x[u + 1] * v[j + (u + 1) * tpr];
                 }
             }
-            for (; j < L; ++j) w0 += p[j * s] * v[j];
-            const double w = tau * (w0 + w1);
-            j = 0;
-            for (; j + 16 <= L; j += 16) {
+            for (; j < L; j += tpr) w0 += p[j * s] * v[j];
+            double w = w0 + w1;
+            for (int o = 1; o < tpr; o *= 2) w += __shfl_xor(w, o, 64);
+            w *= tau_r;
+            j = part;
+            for (; j + 15 * tpr < L; j += 16 * tpr) {
                 double x[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = p[(j + u) * s];
+                for (int u = 0; u < 16; ++u) x[u] = p[(j + u * tpr) * s];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) p[(j + u) * s] = x[u] - w * v[j + u];
+                for (int u = 0; u < 16; ++u) p[(j + u * tpr) * s] = x[u] - w * v[j + u * tpr];
             }
-            for (; j < L; ++j) p[j * s] -= w * v[j];
+            for (; j < L; j += tpr) p[j * s] -= w * v[j];
         }
     }
+    if (G > 1 && !group_barrier(a, k, (int)(2 * t + 1) * G, flag)) return false;
     __syncthreads();
 
     // left reflector: clear column c below the diagonal
     if (tid < L) v[tid] = *at(a, c + tid, c);
     __syncthreads();
-    tau = reflector(v, L, red, &beta);
-    if (tau != 0.0) {
-        if (tid < L) *at(a, c + tid, c) = tid == 0 ? beta : 0.0;
+    const double tau_l = reflector(v, L, red, &beta_l);
+    if (tau_l != 0.0) {
         const int64_t ce = c + 2 * nb < a.n ? c + 2 * nb : a.n;
         const int C = (int)(ce - c - 1);              // columns c+1 .. ce-1
         const double vi = tid < L ? v[tid] : 0.0;
         double* p = tid < L ? at(a, c + tid, c + 1) : nullptr;
         const int cu = tid >> 3, cs = tid & 7;        // column sums: column cu, rows cs + 8 r
-        for (int q0 = 0; q0 < C; q0 += CHUNK) {
+        for (int q0 = g * CHUNK; q0 < C; q0 += G * CHUNK) {
             double x[CHUNK];
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? p[(q0 + u) * s] : 0.0;
@@ -230,7 +260,7 @@ __device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, 
             sum += __shfl_xor(sum, 1, 64);
             sum += __shfl_xor(sum, 2, 64);
             sum += __shfl_xor(sum, 4, 64);
-            if (cs == 0) wq[cu] = tau * sum;
+            if (cs == 0) wq[cu] = tau_l * sum;
             __syncthreads();
             if (tid < L) {
 #pragma unroll
@@ -239,7 +269,13 @@ __device__ void chase_step(const ChaseArgs& a, int64_t k, int64_t t, double* v, 
             }
         }
     }
+    if (G > 1 && !group_barrier(a, k, (int)(2 * t + 2) * G, flag)) return false;
+    if (g == 0) {
+        if (tau_r != 0.0 && tid < L) *at(a, rr, c + tid) = tid == 0 ? beta_r : 0.0;
+        if (tau_l != 0.0 && tid < L) *at(a, c + tid, c) = tid == 0 ? beta_l : 0.0;
+    }
     __syncthreads();
+    return true;
 }
 
 // Reflector of the L <= 64 values x[i ld] (LDS), formed by wave 0 alone: v
@@ -411,11 +447,17 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
     __shared__ double lds[TILE ? 3 * LDS_NB * LDS_LD : CHUNK * PLD + CHUNK];
     __shared__ int sk, flag;
     const int tid = threadIdx.x;
+    const int G = TILE ? 1 : a.group;
     for (;;) {
+        // ticket = sweep * G + member: a group's members are consecutive
+        // tickets, all taken by running workgroups before any of them can
+        // be needed by a later sweep (grid >= G)
         if (tid == 0) sk = __hip_atomic_fetch_add(&a.ctrl[G_HEAD], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int64_t k = __builtin_amdgcn_readfirstlane(sk);
+        const int ticket = __builtin_amdgcn_readfirstlane(sk);
         __syncthreads();
+        const int64_t k = ticket / G;
+        const int g = ticket - (int)k * G;
         if (k >= a.nsweeps) return;
         const int64_t T = nsteps(a.n, a.nb, k);
         const int64_t Tp = k > 0 ? nsteps(a.n, a.nb, k - 1) : 0;
@@ -428,14 +470,16 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 double* Q = lds + ((u + 2) % 3) * LDS_NB * LDS_LD;
                 chase_step_lds(a, k, t, U, D, Q, v, red);   // red[0]: tau
             } else {
-                chase_step(a, k, t, v, red, lds, lds + CHUNK * PLD);
+                if (!chase_step(a, k, t, g, v, red, lds, lds + CHUNK * PLD, &flag)) return;
             }
-            // release: every wave's stores complete and reach the device scope
-            // before the counter moves
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_store(&a.prog[k], (int)(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == 0) {
+                // release: every wave's stores complete and reach the device
+                // scope before the counter moves
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (tid == 0)
+                    __hip_atomic_store(&a.prog[k], (int)(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }
@@ -443,11 +487,14 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
 // Copy the upper band of B into W (zero elsewhere), clear the control words
 // and the progress counters.
 __global__ void pack_kernel(const double* B, int64_t ldb, int64_t n, int nb, double* W, int64_t ldw,
-                            int32_t* ctrl, int32_t* prog, int nsweeps) {
+                            int32_t* ctrl, int32_t* prog, int32_t* bar, int nsweeps) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (g < G_WORDS) ctrl[g] = 0;
-    for (int64_t s = g; s < nsweeps; s += stride) prog[s] = 0;
+    for (int64_t s = g; s < nsweeps; s += stride) {
+        prog[s] = 0;
+        bar[s] = 0;
+    }
     const int64_t total = ldw * n;
     for (int64_t x = g; x < total; x += stride) {
         const int64_t j = x / ldw;
@@ -510,12 +557,14 @@ __global__ void bisect_kernel(const double* d, const double* e, int64_t n, doubl
     sigma[j] = 0.5 * (lo + hi);
 }
 
+// workspace: control words (256 B), the band array (3 nb n doubles), the
+// progress counters and the group barrier counters (one int32 per sweep each)
 inline int64_t ws_prog_off(int64_t n, int nb) { return 256 + (int64_t)3 * nb * n * 8; }
 
 inline int nsweeps_of(int64_t n, int nb) { return nb <= 1 || n <= 2 ? 0 : (int)(n - 2); }
 
 inline size_t ws_bytes(int64_t n, int nb) {
-    return (size_t)(ws_prog_off(n, nb) + ((int64_t)nsweeps_of(n, nb) * 4 + 255) / 256 * 256);
+    return (size_t)(ws_prog_off(n, nb) + 2 * (((int64_t)nsweeps_of(n, nb) * 4 + 255) / 256 * 256));
 }
 
 int device_attr(hipDeviceAttribute_t attr, int fallback) {
@@ -557,16 +606,29 @@ int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double
     a.nsweeps = nsw;
     a.ctrl = (int32_t*)ws;
     a.prog = (int32_t*)((char*)ws + bbg::ws_prog_off(n, nb));
+    a.bar = a.prog + ((int64_t)nsw * 4 + 255) / 256 * 64;
     const double khz = (double)bbg::device_attr(hipDeviceAttributeWallClockRate, 100000);
     a.watchdog_ticks = (int64_t)((watchdog_s > 0 ? watchdog_s : 30.0) * khz * 1000.0);
     const int cus = bbg::device_attr(hipDeviceAttributeMultiprocessorCount, 256);
     const int64_t total = a.ldw * n;
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 8 * (int64_t)cus);
     hipLaunchKernelGGL(bbg::pack_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, B, ldb, n, nb, a.W,
-                       a.ldw, a.ctrl, a.prog, nsw);
+                       a.ldw, a.ctrl, a.prog, a.bar, nsw);
     if (hipGetLastError() != hipSuccess) return BB_EHIP;
+    // nb > GROUP_NB: a group of workgroups a sweep, as many as the CUs left
+    // free by the n / (3 nb) sweeps that can run at once allow, at most
+    // GROUP_MAX (measured at n = 16384: nb = 256 takes 5.8 s with one
+    // workgroup a sweep, 3.1 s with 6, 3.8 s with 8; at nb = 128 no group
+    // size beats one workgroup, whose steps need no group barriers); the
+    // grid holds whole groups and at least one
+    a.group = 1;
+    if (nb > bbg::GROUP_NB) {
+        const int64_t live = n / (3 * (int64_t)nb) + 2;
+        a.group = (int)std::max<int64_t>(1, std::min<int64_t>(bbg::GROUP_MAX, cus / live));
+    }
     if (nsw > 0) {
-        const int grid = std::min(nsw, cus);
+        const int grid = nb <= bbg::LDS_NB ? std::min(nsw, cus)
+                                           : (int)std::min<int64_t>((int64_t)nsw * a.group, cus / a.group * a.group);
         if (nb <= bbg::LDS_NB)
             hipLaunchKernelGGL(bbg::chase_kernel<true>, dim3(grid), dim3(bbg::NT), 0, s, a);
         else
