@@ -15,10 +15,12 @@
 //   * a reflector from the left clears column c below the diagonal; it is
 //     applied to rows c .. c+nb-1 of columns c+1 .. c+2nb-1.
 // Only the first row or column of a bulge is cleared; the rest is cleared
-// by later sweeps.  Step t of sweep k+1 touches an entry that step t+2 of
-// sweep k also touches (row k+1+(t+1)nb, column k+1+(t+2)nb) and nothing of
-// a later step, so it may start once sweep k has finished step t+2: about a
-// third of the steps of a sweep separate consecutive sweeps, and n / (3 nb)
+// by later sweeps.  Step t of sweep k+1 touches one entry that step t+2 of
+// sweep k also touches (row k+1+(t+1)nb, column k+1+(t+2)nb, the first
+// entry of the row that step clears) and nothing of a later step, so it may
+// start once sweep k has finished step t+1 and has written that entry's
+// final value in step t+2 (its progress counter counts half steps): about
+// two and a half steps separate consecutive sweeps, and about n / (2.5 nb)
 // sweeps run at once.
 //
 // One persistent launch: each workgroup takes the next sweep (a ticket from
@@ -154,7 +156,7 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 
 // Step t of sweep k for nb > LDS_NB, on the band array in global memory, by
 // member g of the group of a.group workgroups that runs the sweep.  Only
-// n / (3 nb) sweeps can run at once (21 at n = 16384, nb = 256), so each
+// about n / (2.5 nb) sweeps can run at once (26 at n = 16384, nb = 256), so each
 // sweep's steps are spread over a group to use the other CUs.
 //   * Every member reads row rr and forms the right reflector (the same
 //     arithmetic, the same result); the right update M -= tau (M v) v^T of
@@ -174,6 +176,22 @@ constexpr int GROUP_NB = 128;
 constexpr int GROUP_MAX = 6;
 constexpr int CHUNK = 32;
 constexpr int PLD = NT + 8;              // LDS stride of a product column: lanes 8u+s hit distinct banks
+
+// The half of step t of sweep k that the next sweep waits for: the corner
+// (rr, c), the first entry of the row the right reflector clears, is final
+// (beta; alpha when the row needs no reflector).  Thread 0 stores it (the
+// LDS steps hold a newer value than memory even then), makes it visible
+// and moves the progress counter to 2t+1 (2t+2 marks the whole step).  The
+// step's own stores leave the corner alone afterwards: the next sweep
+// changes it from here on.
+__device__ __forceinline__ void publish_corner(const ChaseArgs& a, int64_t k, int64_t t, double* corner,
+                                               double beta) {
+    if (threadIdx.x == 0) {
+        *corner = beta;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&a.prog[k], (int)(2 * t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 __device__ bool group_barrier(const ChaseArgs& a, int64_t k, int target, int* flag) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");          // in every wave
@@ -197,6 +215,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     __syncthreads();
     double beta_r, beta_l;
     const double tau_r = reflector(v, L, red, &beta_r);
+    if (G == 1) publish_corner(a, k, t, at(a, rr, c), beta_r);
     if (tau_r != 0.0) {
         const int R = (int)(c + L - 1 - rr);          // rows rr+1 .. c+L-1
         const int rpm = (R + G - 1) / G;              // rows of this member: r0 .. r1-1
@@ -235,7 +254,11 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             for (; j < L; j += tpr) p[j * s] -= w * v[j];
         }
     }
-    if (G > 1 && !group_barrier(a, k, (int)(2 * t + 1) * G, flag)) return false;
+    if (G > 1) {
+        // every member has read row rr: its corner may now change
+        if (!group_barrier(a, k, (int)(2 * t + 1) * G, flag)) return false;
+        if (g == 0) publish_corner(a, k, t, at(a, rr, c), beta_r);
+    }
     __syncthreads();
 
     // left reflector: clear column c below the diagonal
@@ -271,7 +294,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     }
     if (G > 1 && !group_barrier(a, k, (int)(2 * t + 2) * G, flag)) return false;
     if (g == 0) {
-        if (tau_r != 0.0 && tid < L) *at(a, rr, c + tid) = tid == 0 ? beta_r : 0.0;
+        if (tau_r != 0.0 && tid >= 1 && tid < L) *at(a, rr, c + tid) = 0.0;   // the corner went out early
         if (tau_l != 0.0 && tid < L) *at(a, c + tid, c) = tid == 0 ? beta_l : 0.0;
     }
     __syncthreads();
@@ -363,6 +386,7 @@ __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double*
     // then rows U u0+1 .. nb-1 and D 0 .. L-1 take M -= tau (M v) v^T
     if (tid < 64) reflector_wave(U + u0, LDS_LD, L, v, sc);
     __syncthreads();
+    publish_corner(a, k, t, const_cast<double*>(db) - nb + u0, U[u0]);
     const int pr = tid >> 1, ph = tid & 1;       // a pair of lanes per row (column): halves of it
     double tau = sc[0];
     if (tau != 0.0) {
@@ -426,7 +450,7 @@ __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double*
 #pragma unroll
         for (int j = 0; j < LDS_J; ++j) {
             const int q = tq + j * cpp;
-            if (q < L) ud[q * s - nb] = U[tr + q * LDS_LD];
+            if (q < L && (q > 0 || tr > u0)) ud[q * s - nb] = U[tr + q * LDS_LD];   // not the corner
         }
     }
     if (mover) {
@@ -462,7 +486,9 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
         const int64_t T = nsteps(a.n, a.nb, k);
         const int64_t Tp = k > 0 ? nsteps(a.n, a.nb, k - 1) : 0;
         for (int64_t t = 0; t < T; ++t) {
-            if (k > 0 && !wait_geq(a, &a.prog[k - 1], (int)(t + 3 < Tp ? t + 3 : Tp), &flag)) return;
+            // the previous sweep's step t+1 done and step t+2 half done
+            // (2t+5), or the whole sweep when it is shorter
+            if (k > 0 && !wait_geq(a, &a.prog[k - 1], (int)(t + 2 < Tp ? 2 * t + 5 : 2 * Tp), &flag)) return;
             if constexpr (TILE) {
                 const int u = (int)((2 * t) % 3);    // Q of step t is U of step t+1
                 double* U = lds + u * LDS_NB * LDS_LD;
@@ -478,7 +504,7 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __syncthreads();
                 if (tid == 0)
-                    __hip_atomic_store(&a.prog[k], (int)(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&a.prog[k], (int)(2 * t + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -616,14 +642,14 @@ int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double
                        a.ldw, a.ctrl, a.prog, a.bar, nsw);
     if (hipGetLastError() != hipSuccess) return BB_EHIP;
     // nb > GROUP_NB: a group of workgroups a sweep, as many as the CUs left
-    // free by the n / (3 nb) sweeps that can run at once allow, at most
+    // free by the n / (2.5 nb) sweeps that can run at once allow, at most
     // GROUP_MAX (measured at n = 16384: nb = 256 takes 5.8 s with one
     // workgroup a sweep, 3.1 s with 6, 3.8 s with 8; at nb = 128 no group
     // size beats one workgroup, whose steps need no group barriers); the
     // grid holds whole groups and at least one
     a.group = 1;
     if (nb > bbg::GROUP_NB) {
-        const int64_t live = n / (3 * (int64_t)nb) + 2;
+        const int64_t live = 2 * n / (5 * (int64_t)nb) + 2;    // sweeps 2.5 steps apart
         a.group = (int)std::max<int64_t>(1, std::min<int64_t>(bbg::GROUP_MAX, cus / live));
     }
     if (nsw > 0) {
