@@ -35,10 +35,10 @@
 // eigenvalues of the 2n x 2n Golub-Kahan matrix, symmetric tridiagonal with
 // a zero diagonal and off-diagonal d1, e1, d2, ..., dn.  A Sturm count (the
 // signs of the pivots of T - x I, safeguarded against zero pivots) gives the
-// number of singular values below x; each thread bisects for one singular
-// value, so all n are found at once (the bisection method of the paper's
-// list of BD2VAL methods, chosen over the serial bidiagonal QR for its
-// parallelism).
+// number of singular values below x; a group of lanes narrows the interval
+// of one singular value by multisection, so all n are found at once (the
+// bisection method of the paper's list of BD2VAL methods, chosen over the
+// serial bidiagonal QR for its parallelism).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -558,9 +558,19 @@ __device__ __forceinline__ int64_t sturm_below(const double* d, const double* e,
     return cnt - n;
 }
 
+// MS lanes per singular value (multisection): each round, lane l counts
+// below x_l = lo + (l+1)(hi-lo)/(MS+1), and the interval shrinks to the
+// one between the largest x with at most s values below it and the
+// smallest x with more, a factor MS+1 a round (about 13 rounds to full
+// precision against 53 for bisection), with MS times the lanes.
+constexpr int MS = 16;
+static_assert(64 % MS == 0, "a value's lanes lie in one wave");
+
 __global__ void bisect_kernel(const double* d, const double* e, int64_t n, double* sigma) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = gt / MS;
+    const int lane = (int)(gt % MS);
+    if (j >= n) return;                 // whole groups leave together (n MS threads are a multiple of MS)
     // Gershgorin bound of T_GK and the pivot floor
     double amax = 0.0, bound = 0.0, prev = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -574,13 +584,23 @@ __global__ void bisect_kernel(const double* d, const double* e, int64_t n, doubl
     const int64_t s = n - 1 - j;     // sigma[j] is the s-th smallest (decreasing order)
     double lo = 0.0, hi = bound * (1.0 + 4.0 * DBL_EPSILON) + pivmin;
     const double abstol = DBL_EPSILON * bound;
-    for (int it = 0; it < 256; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * hi) || mid <= lo || mid >= hi) break;
-        if (sturm_below(d, e, n, mid, pivmin) <= s) lo = mid;
-        else hi = mid;
+    for (int it = 0; it < 128; ++it) {
+        if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * hi)) break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(MS + 1);
+        const bool inside = x > lo && x < hi;
+        const bool below = inside && sturm_below(d, e, n, x, pivmin) <= s;   // x <= sigma_j
+        double nlo = below ? x : lo;
+        double nhi = inside && !below ? x : hi;
+#pragma unroll
+        for (int o = 1; o < MS; o *= 2) {
+            nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+            nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
+        }
+        if (nlo >= nhi || (nlo == lo && nhi == hi)) break;   // counts out of order, or no progress
+        lo = nlo;
+        hi = nhi;
     }
-    sigma[j] = 0.5 * (lo + hi);
+    if (lane == 0) sigma[j] = 0.5 * (lo + hi);
 }
 
 // workspace: control words (256 B), the band array (3 nb n doubles), the
@@ -672,8 +692,9 @@ int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* 
     if (!e && n > 1) return -2;
     if (!sigma && n > 0) return -4;
     if (n == 0) return BB_OK;
-    hipLaunchKernelGGL(bbg::bisect_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, (hipStream_t)stream, d,
-                       e, n, sigma);
+    const int64_t threads = n * bbg::MS;
+    hipLaunchKernelGGL(bbg::bisect_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, d, e, n, sigma);
     return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
 }
 
