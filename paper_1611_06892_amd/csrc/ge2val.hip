@@ -26,10 +26,11 @@
 // One persistent launch: each workgroup takes the next sweep (a ticket from
 // an atomic counter, so a sweep is only ever waited for by a later one that
 // a running workgroup holds: no deadlock for any grid) and runs its steps in
-// order, each after the previous sweep's progress counter allows it.  The
-// counter is published with agent-scope release fences in every wave before
-// a barrier, and read with an agent-scope acquire; a wall-clock watchdog
-// bounds every wait.
+// order, each after the previous sweep's progress counter allows it.  A
+// counter is published after every wave has waited for its own memory
+// operations and the workgroup has met, with one agent-scope release by
+// wave 0, and read with one agent-scope acquire by the polling wave before
+// the workgroup meets; a wall-clock watchdog bounds every wait.
 //
 // BD2VAL.  The singular values of the bidiagonal (d, e) are the positive
 // eigenvalues of the 2n x 2n Golub-Kahan matrix, symmetric tridiagonal with
@@ -147,10 +148,15 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
             __builtin_amdgcn_s_sleep(2);
         }
         if (lane == 0) *flag = ok;
+        // acquire by the polling wave only (invalidate this CU's L1 and the
+        // XCD's non-coherent L2 lines): the other waves wait at the barrier
+        // below with no loads in flight (every step ends in a publication
+        // or group barrier that waits for them) and load only after it, so
+        // one invalidation serves the workgroup
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     const int ok = __builtin_amdgcn_readfirstlane(*flag);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
 }
 
@@ -175,7 +181,14 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 constexpr int GROUP_NB = 128;
 constexpr int GROUP_MAX = 6;
 constexpr int CHUNK = 32;
-constexpr int PLD = NT + 8;              // LDS stride of a product column: lanes 8u+s hit distinct banks
+constexpr int PLD = NT + 8;
+constexpr int RB = 32;                   // loads in flight per thread in the row passes
+
+// A barrier for LDS traffic only: it waits for this wave's LDS operations,
+// not for its global loads, so loads issued before it stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}              // LDS stride of a product column: lanes 8u+s hit distinct banks
 
 // The half of step t of sweep k that the next sweep waits for: the corner
 // (rr, c), the first entry of the row the right reflector clears, is final
@@ -186,17 +199,34 @@ constexpr int PLD = NT + 8;              // LDS stride of a product column: lane
 // changes it from here on.
 __device__ __forceinline__ void publish_corner(const ChaseArgs& a, int64_t k, int64_t t, double* corner,
                                                double beta) {
-    if (threadIdx.x == 0) {
-        *corner = beta;
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0) *corner = beta;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&a.prog[k], (int)(2 * t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&a.prog[k], (int)(2 * t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Publish value through *p after every wave's earlier accesses.  Each wave
+// first waits for its own loads and stores to complete (a completed store
+// has reached the XCD's L2; the barrier alone does not wait for them), the
+// workgroup meets, and wave 0 alone then runs the agent-scope release (L2
+// write-back of dirty lines, then wait) before the relaxed store or add: one
+// L2 write-back a publication instead of one a wave.
+__device__ __forceinline__ void publish_after_barrier(int32_t* p, int value, bool add) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) {
+            if (add) __hip_atomic_fetch_add(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else __hip_atomic_store(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
 __device__ bool group_barrier(const ChaseArgs& a, int64_t k, int target, int* flag) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");          // in every wave
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.bar[k], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    publish_after_barrier(&a.bar[k], 1, true);
     return wait_geq(a, &a.bar[k], target, flag);
 }
 
@@ -229,12 +259,12 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             double* p = at(a, rr + 1 + r, c);
             double w0 = 0.0, w1 = 0.0;
             int j = part;
-            for (; j + 15 * tpr < L; j += 16 * tpr) {
-                double x[16];
+            for (; j + (RB - 1) * tpr < L; j += RB * tpr) {
+                double x[RB];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = p[(j + u * tpr) * s];
+                for (int u = 0; u < RB; ++u) x[u] = p[(j + u * tpr) * s];
 #pragma unroll
-                for (int u = 0; u < 16; u += 2) {
+                for (int u = 0; u < RB; u += 2) {
                     w0 += x[u] * v[j + u * tpr];
                     w1 += x[u + 1] * v[j + (u + 1) * tpr];
                 }
@@ -244,12 +274,12 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             for (int o = 1; o < tpr; o *= 2) w += __shfl_xor(w, o, 64);
             w *= tau_r;
             j = part;
-            for (; j + 15 * tpr < L; j += 16 * tpr) {
-                double x[16];
+            for (; j + (RB - 1) * tpr < L; j += RB * tpr) {
+                double x[RB];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = p[(j + u * tpr) * s];
+                for (int u = 0; u < RB; ++u) x[u] = p[(j + u * tpr) * s];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) p[(j + u * tpr) * s] = x[u] - w * v[j + u * tpr];
+                for (int u = 0; u < RB; ++u) p[(j + u * tpr) * s] = x[u] - w * v[j + u * tpr];
             }
             for (; j < L; j += tpr) p[j * s] -= w * v[j];
         }
@@ -271,25 +301,33 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
         const double vi = tid < L ? v[tid] : 0.0;
         double* p = tid < L ? at(a, c + tid, c + 1) : nullptr;
         const int cu = tid >> 3, cs = tid & 7;        // column sums: column cu, rows cs + 8 r
-        for (int q0 = g * CHUNK; q0 < C; q0 += G * CHUNK) {
-            double x[CHUNK];
+        // the next chunk's loads are issued before this chunk's sums
+        double x[CHUNK];
+        int q0 = g * CHUNK;
 #pragma unroll
-            for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? p[(q0 + u) * s] : 0.0;
+        for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? p[(q0 + u) * s] : 0.0;
+        for (; q0 < C; q0 += G * CHUNK) {
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) P[u * PLD + tid] = vi * x[u];
-            __syncthreads();
+            lds_barrier();
+            const int qn = q0 + G * CHUNK;
+            double y[CHUNK];
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) y[u] = (tid < L && qn + u < C) ? p[(qn + u) * s] : 0.0;
             double sum = 0.0;
             for (int r = cs; r < L; r += 8) sum += P[cu * PLD + r];
             sum += __shfl_xor(sum, 1, 64);
             sum += __shfl_xor(sum, 2, 64);
             sum += __shfl_xor(sum, 4, 64);
             if (cs == 0) wq[cu] = tau_l * sum;
-            __syncthreads();
+            lds_barrier();
             if (tid < L) {
 #pragma unroll
                 for (int u = 0; u < CHUNK; ++u)
                     if (q0 + u < C) p[(q0 + u) * s] = x[u] - vi * wq[u];
             }
+#pragma unroll
+            for (int u = 0; u < CHUNK; ++u) x[u] = y[u];
         }
     }
     if (G > 1 && !group_barrier(a, k, (int)(2 * t + 2) * G, flag)) return false;
@@ -498,14 +536,7 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
             } else {
                 if (!chase_step(a, k, t, g, v, red, lds, lds + CHUNK * PLD, &flag)) return;
             }
-            if (g == 0) {
-                // release: every wave's stores complete and reach the device
-                // scope before the counter moves
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __syncthreads();
-                if (tid == 0)
-                    __hip_atomic_store(&a.prog[k], (int)(2 * t + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (g == 0) publish_after_barrier(&a.prog[k], (int)(2 * t + 2), false);
         }
     }
 }
