@@ -438,7 +438,7 @@ int bb_choose(int64_t m, int64_t n, int nb, const bb_opts* opts, int* tree, int*
  * only entries with 0 <= j - i <= nb are read, B is not written) to upper
  * bidiagonal form U^T B V (U, V orthogonal, V e1 = e1, neither formed) by
  * two-sided Householder bulge chasing, one row per sweep, the sweeps
- * pipelined over the GPU in one persistent launch (for nb > 128 each sweep
+ * pipelined over the GPU in one persistent launch (for nb > 64 each sweep
  * is run by a group of workgroups).  Writes the diagonal
  * d[0..n-1] and the superdiagonal e[0..n-2] (device).  The diagonal and
  * superdiagonal are those of the Golub-Kahan bidiagonalization of B started

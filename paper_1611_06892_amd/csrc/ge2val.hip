@@ -161,7 +161,8 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 }
 
 // Step t of sweep k for nb > LDS_NB, on the band array in global memory, by
-// member g of the group of a.group workgroups that runs the sweep.  Only
+// member g of the group of a.group workgroups that runs the sweep (one
+// workgroup, with no group barriers, when the CUs are all taken).  Only
 // about n / (2.5 nb) sweeps can run at once (26 at n = 16384, nb = 256), so each
 // sweep's steps are spread over a group to use the other CUs.
 //   * Every member reads row rr and forms the right reflector (the same
@@ -178,8 +179,8 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 //     in the step or in the next one, and publishes the step.
 // In the band array entry (i, j+1) follows entry (i, j) at a distance of
 // ldw - 1.  false: an error was reported or the watchdog fired.
-constexpr int GROUP_NB = 128;
-constexpr int GROUP_MAX = 6;
+constexpr int GROUP_NB = 64;
+constexpr int GROUP_MAX = 8;
 constexpr int CHUNK = 32;
 constexpr int PLD = NT + 8;
 constexpr int RB = 32;                   // loads in flight per thread in the row passes
@@ -694,9 +695,9 @@ int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double
     if (hipGetLastError() != hipSuccess) return BB_EHIP;
     // nb > GROUP_NB: a group of workgroups a sweep, as many as the CUs left
     // free by the n / (2.5 nb) sweeps that can run at once allow, at most
-    // GROUP_MAX (measured at n = 16384: nb = 256 takes 5.8 s with one
-    // workgroup a sweep, 3.1 s with 6, 3.8 s with 8; at nb = 128 no group
-    // size beats one workgroup, whose steps need no group barriers); the
+    // GROUP_MAX (measured at n = 16384: nb = 256 takes 1.9 s with 8
+    // workgroups a sweep, 2.3 s with 4; nb = 128 1.5 s with 3 or 4, 1.76 s
+    // with one; at n = 4096, nb = 256: 0.38 s with 8, 0.93 s with one); the
     // grid holds whole groups and at least one
     a.group = 1;
     if (nb > bbg::GROUP_NB) {
