@@ -60,7 +60,7 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
            "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear",
-           "bb_execute_noalloc", "bb_choose", "bb_bnd2bd_workspace", "bb_bnd2bd", "bb_bd2val"]
+           "bb_execute_noalloc", "bb_choose", "bb_bnd2bd_workspace", "bb_bnd2bd", "bb_bnd2bd_group", "bb_bd2val"]
 
 
 def lib():
@@ -149,6 +149,8 @@ def lib():
     L.bb_bnd2bd_workspace.restype = i32
     L.bb_bnd2bd.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, ctypes.c_double, vp]
     L.bb_bnd2bd.restype = i32
+    L.bb_bnd2bd_group.argtypes = [vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp]
+    L.bb_bnd2bd_group.restype = i32
     L.bb_bd2val.argtypes = [vp, vp, i64, vp, vp]
     L.bb_bd2val.restype = i32
     L.bb_cache_clear.argtypes = []
@@ -433,8 +435,9 @@ def bnd2bd_workspace(n, nb) -> int:
     return b.value
 
 
-def bnd2bd(S, ldb, n, nb, ws=None, watchdog_s=0.0, stream=None, check=True):
-    """Band to bidiagonal (bb_bnd2bd).  S: CUDA FP64 storage of a column-major
+def bnd2bd(S, ldb, n, nb, ws=None, watchdog_s=0.0, stream=None, check=True, group=0):
+    """Band to bidiagonal (bb_bnd2bd, or bb_bnd2bd_group with group > 0: the
+    workgroups per sweep for nb > 64).  S: CUDA FP64 storage of a column-major
     matrix whose leading n x n part holds the upper band of bandwidth nb
     (leading dimension ldb), e.g. the storage tensor a Plan reduced.
     Returns (d, e) as CUDA tensors; S is not modified."""
@@ -444,10 +447,10 @@ def bnd2bd(S, ldb, n, nb, ws=None, watchdog_s=0.0, stream=None, check=True):
         ws = torch.empty(max(bnd2bd_workspace(n, nb), 8), dtype=torch.uint8, device=dev)
     d = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
-    _check(lib().bb_bnd2bd(ctypes.c_void_p(S.data_ptr()), int(ldb), int(n), int(nb),
-                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
-                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), float(watchdog_s),
-                           _stream_handle(stream)), "bb_bnd2bd")
+    _check(lib().bb_bnd2bd_group(ctypes.c_void_p(S.data_ptr()), int(ldb), int(n), int(nb),
+                                 ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), float(watchdog_s), int(group),
+                                 _stream_handle(stream)), "bb_bnd2bd_group")
     if check:
         st = poll_error(ws, stream)
         if st != 0:

@@ -168,7 +168,9 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 //   * Every member reads row rr and forms the right reflector (the same
 //     arithmetic, the same result); the right update M -= tau (M v) v^T of
 //     rows rr+1 .. c+L-1 of columns c .. c+L-1 is split by rows, TPR lanes a
-//     row, in two passes (the row products, then the update).
+//     row, in two passes (the row products, then the update).  Every sum
+//     is taken in the same order whatever the group size, so the result
+//     does not depend on it.
 //   * Group barrier: column c is final.
 //   * Every member reads column c and forms the left reflector; the left
 //     update M -= tau v (v^T M) of rows c .. c+L-1 of columns c+1 .. ce-1 is
@@ -184,6 +186,7 @@ constexpr int GROUP_MAX = 8;
 constexpr int CHUNK = 32;
 constexpr int PLD = NT + 8;
 constexpr int RB = 32;                   // loads in flight per thread in the row passes
+constexpr int TPR = 4;                   // lanes a row in the right update
 
 // A barrier for LDS traffic only: it waits for this wave's LDS operations,
 // not for its global loads, so loads issued before it stay in flight.
@@ -251,8 +254,9 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
         const int R = (int)(c + L - 1 - rr);          // rows rr+1 .. c+L-1
         const int rpm = (R + G - 1) / G;              // rows of this member: r0 .. r1-1
         const int r0 = g * rpm, r1 = r0 + rpm < R ? r0 + rpm : R;
-        int tpr = 1;                                  // lanes a row: a power of two <= 8
-        while (tpr < 8 && 2 * tpr * rpm <= NT) tpr *= 2;
+        // TPR lanes a row whatever the group size, so that every row's
+        // products are summed in the same order for any group
+        constexpr int tpr = TPR;
         const int part = tid & (tpr - 1);
         // the tpr lanes of a row are adjacent and share its loop trips, so
         // the shuffles that sum their parts stay within active lanes
@@ -663,8 +667,9 @@ int bb_bnd2bd_workspace(int64_t n, int nb, size_t* ws_bytes) {
     return BB_OK;
 }
 
-int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
-              size_t ws_bytes, double watchdog_s, void* stream) {
+int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
+                    size_t ws_bytes, double watchdog_s, int group, void* stream) {
+    if (group < 0 || group > bbg::GROUP_MAX) return -10;
     if (n < 0) return -3;
     if (!B && n > 0) return -1;
     if (ldb < (n > 1 ? n : 1)) return -2;
@@ -703,6 +708,7 @@ int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double
     if (nb > bbg::GROUP_NB) {
         const int64_t live = 2 * n / (5 * (int64_t)nb) + 2;    // sweeps 2.5 steps apart
         a.group = (int)std::max<int64_t>(1, std::min<int64_t>(bbg::GROUP_MAX, cus / live));
+        if (group > 0) a.group = std::min(group, cus);
     }
     if (nsw > 0) {
         const int grid = nb <= bbg::LDS_NB ? std::min(nsw, cus)
@@ -716,6 +722,11 @@ int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double
     hipLaunchKernelGGL(bbg::extract_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.W, a.ldw, n,
                        nb, d, e);
     return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
+}
+
+int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
+              size_t ws_bytes, double watchdog_s, void* stream) {
+    return bb_bnd2bd_group(B, ldb, n, nb, d, e, ws, ws_bytes, watchdog_s, 0, stream);
 }
 
 int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* stream) {
