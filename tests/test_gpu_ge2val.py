@@ -193,3 +193,29 @@ def test_bnd2bd_group_out_of_range(bb):
     S = torch.zeros(10, 10, dtype=torch.float64, device="cuda")
     with pytest.raises(bb.BidiagError):
         bb.bnd2bd(S, 10, 10, 8, group=9)
+
+
+@pytest.mark.parametrize("nb,tree", [(256, "auto"), (128, "greedy")])
+def test_ge2val_full_size_square_graded(bb, nb, tree):
+    """The 16384 x 16384 graded square (s geometric 1 .. 1e-6) through
+    GE2BND, BND2BD and BD2VAL in the launch configuration the bench times:
+    every singular value against the prescribed one within 50 n eps s_1
+    (Weyl), and the bidiagonal's Frobenius norm against ||s||."""
+    cfg = workloads.CONFIGS["square_graded"]
+    m, n = cfg["m"], cfg["n"]
+    Ad, s = workloads.graded_device(m, n, *cfg["seeds"], cfg["smin"])
+    S = bb.to_colmajor(Ad)
+    del Ad
+    plan = bb.Plan(m, n, nb, tree, "bidiag", watchdog_s=60.0)
+    vt, ws = plan.alloc()
+    print("case ge2val 16384^2 nb", nb, tree, flush=True)
+    plan.execute(S, m, vt, ws)
+    assert bb.poll_error(ws) == 0
+    del vt, ws
+    d, e = bb.bnd2bd(S, m, n, nb, watchdog_s=60.0)
+    sig = bb.bd2val(d, e).cpu().numpy()
+    ref = np.sort(np.asarray(s))[::-1]
+    tol = 50 * n * EPS * ref[0]
+    assert np.max(np.abs(sig - ref)) <= tol
+    fro = np.sqrt(np.sum(d.cpu().numpy() ** 2) + np.sum(e.cpu().numpy() ** 2))
+    assert abs(fro - np.linalg.norm(ref)) <= tol * np.sqrt(n)
