@@ -198,7 +198,9 @@ __device__ __forceinline__ void lds_barrier() {
 // (rr, c), the first entry of the row the right reflector clears, is final
 // (beta; alpha when the row needs no reflector).  Thread 0 stores it (the
 // LDS steps hold a newer value than memory even then), makes it visible
-// and moves the progress counter to 2t+1 (2t+2 marks the whole step).  The
+// and moves the progress counter to 2t+1; the release also covers every
+// earlier store of the sweep, which each wave has waited for before the
+// preceding barrier (2T marks the whole sweep).  The
 // step's own stores leave the corner alone afterwards: the next sweep
 // changes it from here on.
 __device__ __forceinline__ void publish_corner(const ChaseArgs& a, int64_t k, int64_t t, double* corner,
@@ -244,8 +246,11 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     const int L = (int)(a.n - c < nb ? a.n - c : nb);
     const int64_t s = a.ldw - 1;
 
-    // right reflector: clear row rr beyond column c
+    // right reflector: clear row rr beyond column c; the previous step's
+    // stores complete in every wave before the reflector's barriers, so the
+    // corner's release below covers them too
     if (tid < L) v[tid] = *at(a, rr, c + tid);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     double beta_r, beta_l;
     const double tau_r = reflector(v, L, red, &beta_r);
@@ -428,6 +433,9 @@ __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double*
     // right reflector (wave 0): clear row rr (U row u0) beyond column c;
     // then rows U u0+1 .. nb-1 and D 0 .. L-1 take M -= tau (M v) v^T
     if (tid < 64) reflector_wave(U + u0, LDS_LD, L, v, sc);
+    // the previous step's stores complete in every wave before the barrier,
+    // so wave 0's release in publish_corner covers them too
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     publish_corner(a, k, t, const_cast<double*>(db) - nb + u0, U[u0]);
     const int pr = tid >> 1, ph = tid & 1;       // a pair of lanes per row (column): halves of it
@@ -541,7 +549,13 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
             } else {
                 if (!chase_step(a, k, t, g, v, red, lds, lds + CHUNK * PLD, &flag)) return;
             }
-            if (g == 0) publish_after_barrier(&a.prog[k], (int)(2 * t + 2), false);
+            // The next sweep waits for half steps (2t+5: step t+1 done, the
+            // corner of step t+2 final), whose release also covers every
+            // earlier store of the sweep; only the last step is published
+            // whole (2T).  The barrier keeps a step's LDS buffers until
+            // every wave has stored them.
+            if (g == 0 && t + 1 == T) publish_after_barrier(&a.prog[k], (int)(2 * T), false);
+            else __syncthreads();
         }
     }
 }
