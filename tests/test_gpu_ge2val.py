@@ -219,3 +219,23 @@ def test_ge2val_full_size_square_graded(bb, nb, tree):
     assert np.max(np.abs(sig - ref)) <= tol
     fro = np.sqrt(np.sum(d.cpu().numpy() ** 2) + np.sum(e.cpu().numpy() ** 2))
     assert abs(fro - np.linalg.norm(ref)) <= tol * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n,nb", [(2000, 32), (1500, 128)])
+def test_bnd2bd_watchdog_reports_timeout_and_recovers(bb, n, nb):
+    """A watchdog of (almost) no clock ticks, set from the host: the first
+    wait that is not satisfied at once reports BB_ETIMEOUT, every workgroup
+    sees the error word and leaves (the launch ends normally), and the next
+    call on the same workspace gives the oracle's bidiagonal."""
+    print("case bnd2bd watchdog", n, nb, flush=True)
+    A = band_input("square", n, nb, 7400 + n)
+    S, ld = colmajor(A)
+    ws = torch.empty(bb.bnd2bd_workspace(n, nb), dtype=torch.uint8, device="cuda")
+    with pytest.raises(bb.BidiagError) as err:
+        bb.bnd2bd(S, ld, n, nb, ws=ws, watchdog_s=1e-12)
+    assert err.value.code == bb.poll_error(ws) == 3          # BB_ETIMEOUT
+    d, e = bb.bnd2bd(S, ld, n, nb, ws=ws, watchdog_s=20.0)
+    do, eo = og.bnd2bd(A, nb)
+    tol = 50 * n * EPS * np.linalg.norm(og.upper_band(A, n, nb))
+    assert np.max(np.abs(np.abs(d.cpu().numpy()) - np.abs(do))) <= tol
+    assert np.max(np.abs(np.abs(e.cpu().numpy()) - np.abs(eo))) <= tol
