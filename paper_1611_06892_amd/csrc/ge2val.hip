@@ -26,11 +26,12 @@
 // One persistent launch: each workgroup takes the next sweep (a ticket from
 // an atomic counter, so a sweep is only ever waited for by a later one that
 // a running workgroup holds: no deadlock for any grid) and runs its steps in
-// order, each after the previous sweep's progress counter allows it.  A
-// counter is published after every wave has waited for its own memory
-// operations and the workgroup has met, with one agent-scope release by
-// wave 0, and read with one agent-scope acquire by the polling wave before
-// the workgroup meets; a wall-clock watchdog bounds every wait.
+// order, each after the previous sweep's progress counter allows it.  The
+// band array is written with agent-scope stores (past the XCD's L2), so a
+// counter is published once every wave has waited for its own memory
+// operations and the workgroup has met, with no L2 write-back, and read
+// with one agent-scope acquire by the polling wave before the workgroup
+// meets; a wall-clock watchdog bounds every wait.
 //
 // BD2VAL.  The singular values of the bidiagonal (d, e) are the positive
 // eigenvalues of the 2n x 2n Golub-Kahan matrix, symmetric tridiagonal with
@@ -75,6 +76,14 @@ __host__ __device__ inline int64_t nsteps(int64_t n, int nb, int64_t k) {
 
 __device__ __forceinline__ double* at(const ChaseArgs& a, int64_t i, int64_t j) {
     return a.W + (i - j + 2 * a.nb - 1) + j * a.ldw;
+}
+
+// Stores to the band array: agent-scope stores, performed past the XCD's L2
+// at the device's coherence point, so no L2 line of the band array is ever
+// dirty and a publication needs no L2 write-back, only each wave's wait for
+// its own stores (the same protocol as the band reduction's scheduler).
+__device__ __forceinline__ void st(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int aload(const int32_t* p) {
@@ -197,33 +206,31 @@ __device__ __forceinline__ void lds_barrier() {
 // The half of step t of sweep k that the next sweep waits for: the corner
 // (rr, c), the first entry of the row the right reflector clears, is final
 // (beta; alpha when the row needs no reflector).  Thread 0 stores it (the
-// LDS steps hold a newer value than memory even then), makes it visible
-// and moves the progress counter to 2t+1; the release also covers every
-// earlier store of the sweep, which each wave has waited for before the
+// LDS steps hold a newer value than memory even then), waits for the store
+// and moves the progress counter to 2t+1; every earlier store of the sweep
+// has completed too, each wave having waited for its own before the
 // preceding barrier (2T marks the whole sweep).  The
 // step's own stores leave the corner alone afterwards: the next sweep
 // changes it from here on.
 __device__ __forceinline__ void publish_corner(const ChaseArgs& a, int64_t k, int64_t t, double* corner,
                                                double beta) {
     if (threadIdx.x < 64) {
-        if (threadIdx.x == 0) *corner = beta;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) st(corner, beta);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         if (threadIdx.x == 0)
             __hip_atomic_store(&a.prog[k], (int)(2 * t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // Publish value through *p after every wave's earlier accesses.  Each wave
-// first waits for its own loads and stores to complete (a completed store
-// has reached the XCD's L2; the barrier alone does not wait for them), the
-// workgroup meets, and wave 0 alone then runs the agent-scope release (L2
-// write-back of dirty lines, then wait) before the relaxed store or add: one
-// L2 write-back a publication instead of one a wave.
+// first waits for its own loads and stores to complete (the barrier alone
+// does not wait for them; the band array's stores are agent-scope, so a
+// completed one has been performed past the XCD's L2 and no write-back is
+// needed), the workgroup meets, and thread 0 stores or adds.
 __device__ __forceinline__ void publish_after_barrier(int32_t* p, int value, bool add) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x < 64) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (threadIdx.x == 0) {
             if (add) __hip_atomic_fetch_add(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else __hip_atomic_store(p, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -289,9 +296,9 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
 #pragma unroll
                 for (int u = 0; u < RB; ++u) x[u] = p[(j + u * tpr) * s];
 #pragma unroll
-                for (int u = 0; u < RB; ++u) p[(j + u * tpr) * s] = x[u] - w * v[j + u * tpr];
+                for (int u = 0; u < RB; ++u) st(p + (j + u * tpr) * s, x[u] - w * v[j + u * tpr]);
             }
-            for (; j < L; j += tpr) p[j * s] -= w * v[j];
+            for (; j < L; j += tpr) st(p + j * s, p[j * s] - w * v[j]);
         }
     }
     if (G > 1) {
@@ -334,7 +341,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             if (tid < L) {
 #pragma unroll
                 for (int u = 0; u < CHUNK; ++u)
-                    if (q0 + u < C) p[(q0 + u) * s] = x[u] - vi * wq[u];
+                    if (q0 + u < C) st(p + (q0 + u) * s, x[u] - vi * wq[u]);
             }
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) x[u] = y[u];
@@ -342,8 +349,8 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     }
     if (G > 1 && !group_barrier(a, k, (int)(2 * t + 2) * G, flag)) return false;
     if (g == 0) {
-        if (tau_r != 0.0 && tid >= 1 && tid < L) *at(a, rr, c + tid) = 0.0;   // the corner went out early
-        if (tau_l != 0.0 && tid < L) *at(a, c + tid, c) = tid == 0 ? beta_l : 0.0;
+        if (tau_r != 0.0 && tid >= 1 && tid < L) st(at(a, rr, c + tid), 0.0);   // the corner went out early
+        if (tau_l != 0.0 && tid < L) st(at(a, c + tid, c), tid == 0 ? beta_l : 0.0);
     }
     __syncthreads();
     return true;
@@ -501,14 +508,14 @@ __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double*
 #pragma unroll
         for (int j = 0; j < LDS_J; ++j) {
             const int q = tq + j * cpp;
-            if (q < L && (q > 0 || tr > u0)) ud[q * s - nb] = U[tr + q * LDS_LD];   // not the corner
+            if (q < L && (q > 0 || tr > u0)) st(ud + q * s - nb, U[tr + q * LDS_LD]);   // not the corner
         }
     }
     if (mover) {
 #pragma unroll
         for (int j = 0; j < LDS_J; ++j) {
             const int q = tq + j * cpp;
-            if (q < L) ud[q * s] = D[tr + q * LDS_LD];
+            if (q < L) st(ud + q * s, D[tr + q * LDS_LD]);
         }
     }
 }
