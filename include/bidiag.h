@@ -464,8 +464,8 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
 /*
  * bb_bd2val -- BD2VAL: the singular values of the upper bidiagonal with
  * diagonal d[0..n-1] and superdiagonal e[0..n-2] (device), in decreasing
- * order, into sigma[0..n-1] (device).  Bisection (multisection, 16 lanes
- * per singular value) on the Sturm counts of the 2n x 2n Golub-Kahan
+ * order, into sigma[0..n-1] (device).  Bisection (multisection, 4 to 32
+ * lanes per singular value) on the Sturm counts of the 2n x 2n Golub-Kahan
  * tridiagonal, all values at once, to an absolute accuracy of a few
  * eps * ||B||.  Arguments: d (1), e (2), n >= 0
  * (3), sigma (4), stream (5).  Asynchronous; no workspace.

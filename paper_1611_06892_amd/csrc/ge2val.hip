@@ -618,12 +618,15 @@ __device__ __forceinline__ int64_t sturm_below(const double* d, const double* e,
 // MS lanes per singular value (multisection): each round, lane l counts
 // below x_l = lo + (l+1)(hi-lo)/(MS+1), and the interval shrinks to the
 // one between the largest x with at most s values below it and the
-// smallest x with more, a factor MS+1 a round (about 13 rounds to full
-// precision against 53 for bisection), with MS times the lanes.
-constexpr int MS = 16;
-static_assert(64 % MS == 0, "a value's lanes lie in one wave");
+// smallest x with more, a factor MS+1 a round (13 rounds to full precision
+// at MS = 16, against 53 for bisection), with MS times the lanes.  The host
+// picks MS so that about MS_LANES lanes run (measured: n = 16384 76 ms at
+// MS = 8, 92 ms at 4 and 16; n = 4096 13 ms at 16 or 32, 23 ms at 4).
+constexpr int MS_LANES = 1 << 17;
 
+template <int MS>
 __global__ void bisect_kernel(const double* d, const double* e, int64_t n, double* sigma) {
+    static_assert(64 % MS == 0, "a value's lanes lie in one wave");
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t j = gt / MS;
     const int lane = (int)(gt % MS);
@@ -756,9 +759,16 @@ int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* 
     if (!e && n > 1) return -2;
     if (!sigma && n > 0) return -4;
     if (n == 0) return BB_OK;
-    const int64_t threads = n * bbg::MS;
-    hipLaunchKernelGGL(bbg::bisect_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, d, e, n, sigma);
+    int ms = 4;
+    while (ms < 32 && n * ms < bbg::MS_LANES) ms *= 2;
+    const dim3 grid((unsigned)((n * ms + 255) / 256));
+    hipStream_t s = (hipStream_t)stream;
+    switch (ms) {
+        case 4: hipLaunchKernelGGL(bbg::bisect_kernel<4>, grid, dim3(256), 0, s, d, e, n, sigma); break;
+        case 8: hipLaunchKernelGGL(bbg::bisect_kernel<8>, grid, dim3(256), 0, s, d, e, n, sigma); break;
+        case 16: hipLaunchKernelGGL(bbg::bisect_kernel<16>, grid, dim3(256), 0, s, d, e, n, sigma); break;
+        default: hipLaunchKernelGGL(bbg::bisect_kernel<32>, grid, dim3(256), 0, s, d, e, n, sigma); break;
+    }
     return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
 }
 
