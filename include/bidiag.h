@@ -455,9 +455,9 @@ int bb_bnd2bd_workspace(int64_t n, int nb, size_t* ws_bytes);
 int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
               size_t ws_bytes, double watchdog_s, void* stream);
 /* bb_bnd2bd_group -- bb_bnd2bd with the number of workgroups that run each
- * sweep for nb > 64 given: group (10) in 1..8, 0 = chosen from the device's
- * CU count as bb_bnd2bd does (ignored for nb <= 64, where one workgroup runs a
- * sweep).  The result does not depend on it.  -10 for group out of range. */
+ * sweep for nb > 64 given: group (10) in 1..16, 0 = ceil(nb / 16) as
+ * bb_bnd2bd uses (ignored for nb <= 64, where one workgroup runs a sweep).
+ * The result does not depend on it.  -10 for group out of range. */
 int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
                     size_t ws_bytes, double watchdog_s, int group, void* stream);
 

@@ -170,8 +170,8 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 }
 
 // Step t of sweep k for nb > LDS_NB, on the band array in global memory, by
-// member g of the group of a.group workgroups that runs the sweep (one
-// workgroup, with no group barriers, when the CUs are all taken).  Only
+// member g of the group of a.group workgroups that runs the sweep (with
+// a group of one, as bb_bnd2bd_group allows, no group barriers).  Only
 // about n / (2.5 nb) sweeps can run at once (26 at n = 16384, nb = 256), so each
 // sweep's steps are spread over a group to use the other CUs.
 //   * Every member reads row rr and forms the right reflector (the same
@@ -191,7 +191,7 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 // In the band array entry (i, j+1) follows entry (i, j) at a distance of
 // ldw - 1.  false: an error was reported or the watchdog fired.
 constexpr int GROUP_NB = 64;
-constexpr int GROUP_MAX = 8;
+constexpr int GROUP_MAX = 16;
 constexpr int CHUNK = 32;
 constexpr int PLD = NT + 8;
 constexpr int RB = 32;                   // loads in flight per thread in the row passes
@@ -722,16 +722,15 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
     hipLaunchKernelGGL(bbg::pack_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, B, ldb, n, nb, a.W,
                        a.ldw, a.ctrl, a.prog, a.bar, nsw);
     if (hipGetLastError() != hipSuccess) return BB_EHIP;
-    // nb > GROUP_NB: a group of workgroups a sweep, as many as the CUs left
-    // free by the n / (2.5 nb) sweeps that can run at once allow, at most
-    // GROUP_MAX (measured at n = 16384: nb = 256 takes 1.9 s with 8
-    // workgroups a sweep, 2.3 s with 4; nb = 128 1.5 s with 3 or 4, 1.76 s
-    // with one; at n = 4096, nb = 256: 0.38 s with 8, 0.93 s with one); the
-    // grid holds whole groups and at least one
+    // nb > GROUP_NB: a group of ceil(nb / 16) workgroups a sweep, so that a
+    // member takes about 32 rows of the right update and one 32-column chunk
+    // of the left one (measured at n = 16384: nb = 256 1.35 s with 16
+    // workgroups a sweep, 1.60 s with 8, 2.64 s with 4; nb = 128 1.01 s with
+    // 8, 1.06 s with 4, 1.58 s with 12); the grid holds whole groups, at
+    // least one
     a.group = 1;
     if (nb > bbg::GROUP_NB) {
-        const int64_t live = 2 * n / (5 * (int64_t)nb) + 2;    // sweeps 2.5 steps apart
-        a.group = (int)std::max<int64_t>(1, std::min<int64_t>(bbg::GROUP_MAX, cus / live));
+        a.group = std::min(std::min((nb + 15) / 16, bbg::GROUP_MAX), cus);
         if (group > 0) a.group = std::min(group, cus);
     }
     if (nsw > 0) {

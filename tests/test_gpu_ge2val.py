@@ -175,12 +175,12 @@ def test_ge2val_band_stage_matches_oracle_on_the_device_band(bb):
 def test_bnd2bd_result_does_not_depend_on_group_size(bb, n, nb):
     """For nb > 64 a sweep runs on a group of workgroups (rows and column
     chunks shared out, reflectors formed by every member): one workgroup a
-    sweep (no group barriers), 2, 3 and 8 give the same bits, and match the
+    sweep (no group barriers), 2, 3, 8 and 16 give the same bits, and match the
     oracle."""
     print("case bnd2bd groups", n, nb, flush=True)
     A = band_input("tall", n, nb, 7300 + n)
     S, ld = colmajor(A)
-    res = [bb.bnd2bd(S, ld, n, nb, watchdog_s=20.0, group=g) for g in (1, 2, 3, 8)]
+    res = [bb.bnd2bd(S, ld, n, nb, watchdog_s=20.0, group=g) for g in (1, 2, 3, 8, 16)]
     for d, e in res[1:]:
         assert torch.equal(d, res[0][0]) and torch.equal(e, res[0][1])
     do, eo = og.bnd2bd(A, nb)
@@ -192,7 +192,7 @@ def test_bnd2bd_result_does_not_depend_on_group_size(bb, n, nb):
 def test_bnd2bd_group_out_of_range(bb):
     S = torch.zeros(10, 10, dtype=torch.float64, device="cuda")
     with pytest.raises(bb.BidiagError):
-        bb.bnd2bd(S, 10, 10, 8, group=9)
+        bb.bnd2bd(S, 10, 10, 8, group=17)
 
 
 @pytest.mark.parametrize("nb,tree", [(256, "auto"), (128, "greedy")])
