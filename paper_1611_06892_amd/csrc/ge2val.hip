@@ -27,11 +27,12 @@
 // an atomic counter, so a sweep is only ever waited for by a later one that
 // a running workgroup holds: no deadlock for any grid) and runs its steps in
 // order, each after the previous sweep's progress counter allows it.  The
-// band array is written with agent-scope stores (past the XCD's L2), so a
-// counter is published once every wave has waited for its own memory
-// operations and the workgroup has met, with no L2 write-back, and read
-// with one agent-scope acquire by the polling wave before the workgroup
-// meets; a wall-clock watchdog bounds every wait.
+// band array is written and read with agent-scope stores and loads (past the
+// XCD's L2, at the coherence point), so a counter is published once every
+// wave has waited for its own memory operations and the workgroup has met,
+// with no L2 write-back, and the loads that follow a counter's load see every
+// store performed before it was written, with no L2 invalidation; a
+// wall-clock watchdog bounds every wait.
 //
 // BD2VAL.  The singular values of the bidiagonal (d, e) are the positive
 // eigenvalues of the 2n x 2n Golub-Kahan matrix, symmetric tridiagonal with
@@ -84,6 +85,13 @@ __device__ __forceinline__ double* at(const ChaseArgs& a, int64_t i, int64_t j) 
 // its own stores (the same protocol as the band reduction's scheduler).
 __device__ __forceinline__ void st(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads from the band array: agent-scope loads, served at the coherence
+// point, so they see every store that completed before the progress counter
+// they follow was written, with no L2 invalidation.
+__device__ __forceinline__ double ld(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int aload(const int32_t* p) {
@@ -157,12 +165,8 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
             __builtin_amdgcn_s_sleep(2);
         }
         if (lane == 0) *flag = ok;
-        // acquire by the polling wave only (invalidate this CU's L1 and the
-        // XCD's non-coherent L2 lines): the other waves wait at the barrier
-        // below with no loads in flight (every step ends in a publication
-        // or group barrier that waits for them) and load only after it, so
-        // one invalidation serves the workgroup
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // no acquire: the band array is read with agent-scope loads, issued
+        // only after this load of the counter has returned
     }
     __syncthreads();
     const int ok = __builtin_amdgcn_readfirstlane(*flag);
@@ -256,7 +260,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     // right reflector: clear row rr beyond column c; the previous step's
     // stores complete in every wave before the reflector's barriers, so the
     // corner's release below covers them too
-    if (tid < L) v[tid] = *at(a, rr, c + tid);
+    if (tid < L) v[tid] = ld(at(a, rr, c + tid));
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     double beta_r, beta_l;
@@ -279,14 +283,14 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             for (; j + (RB - 1) * tpr < L; j += RB * tpr) {
                 double x[RB];
 #pragma unroll
-                for (int u = 0; u < RB; ++u) x[u] = p[(j + u * tpr) * s];
+                for (int u = 0; u < RB; ++u) x[u] = ld(p + (j + u * tpr) * s);
 #pragma unroll
                 for (int u = 0; u < RB; u += 2) {
                     w0 += x[u] * v[j + u * tpr];
                     w1 += x[u + 1] * v[j + (u + 1) * tpr];
                 }
             }
-            for (; j < L; j += tpr) w0 += p[j * s] * v[j];
+            for (; j < L; j += tpr) w0 += ld(p + j * s) * v[j];
             double w = w0 + w1;
             for (int o = 1; o < tpr; o *= 2) w += __shfl_xor(w, o, 64);
             w *= tau_r;
@@ -294,11 +298,11 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             for (; j + (RB - 1) * tpr < L; j += RB * tpr) {
                 double x[RB];
 #pragma unroll
-                for (int u = 0; u < RB; ++u) x[u] = p[(j + u * tpr) * s];
+                for (int u = 0; u < RB; ++u) x[u] = ld(p + (j + u * tpr) * s);
 #pragma unroll
                 for (int u = 0; u < RB; ++u) st(p + (j + u * tpr) * s, x[u] - w * v[j + u * tpr]);
             }
-            for (; j < L; j += tpr) st(p + j * s, p[j * s] - w * v[j]);
+            for (; j < L; j += tpr) st(p + j * s, ld(p + j * s) - w * v[j]);
         }
     }
     if (G > 1) {
@@ -309,7 +313,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
     __syncthreads();
 
     // left reflector: clear column c below the diagonal
-    if (tid < L) v[tid] = *at(a, c + tid, c);
+    if (tid < L) v[tid] = ld(at(a, c + tid, c));
     __syncthreads();
     const double tau_l = reflector(v, L, red, &beta_l);
     if (tau_l != 0.0) {
@@ -322,7 +326,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
         double x[CHUNK];
         int q0 = g * CHUNK;
 #pragma unroll
-        for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? p[(q0 + u) * s] : 0.0;
+        for (int u = 0; u < CHUNK; ++u) x[u] = (tid < L && q0 + u < C) ? ld(p + (q0 + u) * s) : 0.0;
         for (; q0 < C; q0 += G * CHUNK) {
 #pragma unroll
             for (int u = 0; u < CHUNK; ++u) P[u * PLD + tid] = vi * x[u];
@@ -330,7 +334,7 @@ __device__ bool chase_step(const ChaseArgs& a, int64_t k, int64_t t, int g, doub
             const int qn = q0 + G * CHUNK;
             double y[CHUNK];
 #pragma unroll
-            for (int u = 0; u < CHUNK; ++u) y[u] = (tid < L && qn + u < C) ? p[(qn + u) * s] : 0.0;
+            for (int u = 0; u < CHUNK; ++u) y[u] = (tid < L && qn + u < C) ? ld(p + (qn + u) * s) : 0.0;
             double sum = 0.0;
             for (int r = cs; r < L; r += 8) sum += P[cu * PLD + r];
             sum += __shfl_xor(sum, 1, 64);
@@ -420,12 +424,12 @@ __device__ void chase_step_lds(const ChaseArgs& a, int64_t k, int64_t t, double*
     const double* q0p = d0 - nb + (int64_t)nb * a.ldw;
     {
         double xd[LDS_J], xq[LDS_J];
-        const double xu = t == 0 && tid < L ? db[tid * s - 1] : 0.0;     // U(nb-1, tid): the row k
+        const double xu = t == 0 && tid < L ? ld(db + tid * s - 1) : 0.0;     // U(nb-1, tid): the row k
 #pragma unroll
         for (int j = 0; j < LDS_J; ++j) {
             const int q = tq + j * cpp;
-            xd[j] = mover && q < L ? d0[q * s] : 0.0;
-            xq[j] = mover && q < Lq ? q0p[q * s] : 0.0;
+            xd[j] = mover && q < L ? ld(d0 + q * s) : 0.0;
+            xq[j] = mover && q < Lq ? ld(q0p + q * s) : 0.0;
         }
         if (t == 0 && tid < L) U[(nb - 1) + tid * LDS_LD] = xu;
 #pragma unroll
