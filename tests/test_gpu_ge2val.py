@@ -55,7 +55,9 @@ def band_input(kind, n, nb, seed):
 @pytest.mark.parametrize("n,nb,kind", [(1, 1, "tall"), (2, 3, "tall"), (3, 2, "square"), (9, 1, "tall"),
                                        (5, 2, "tall"), (64, 8, "square"), (100, 16, "tall"),
                                        (257, 32, "graded"), (300, 64, "tall"), (513, 64, "tall"),
-                                       (640, 128, "tall"), (700, 256, "graded"), (1000, 32, "tall")])
+                                       (640, 128, "tall"), (700, 256, "graded"), (1000, 32, "tall"),
+                                       (50, 100, "square"), (129, 200, "tall"), (257, 256, "square"),
+                                       (66, 65, "graded")])
 def test_bnd2bd_matches_oracle(bb, n, nb, kind):
     print("case bnd2bd", n, nb, kind, flush=True)
     A = band_input(kind, n, nb, 7000 + n + nb)
