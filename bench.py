@@ -114,6 +114,58 @@ def oracle_rate(m, n, nb, seeds, smin, threads=None):
     return json.loads(out.decode().strip().splitlines()[-1])
 
 
+ORACLE_CFG_SNIPPET = r"""
+import sys, time, json
+sys.path.insert(0, %r)
+import oracle, workloads
+m, n, nb, variant, kind, seeds, smin = %d, %d, %d, %r, %r, (%d, %d), %r
+if kind == "graded":
+    A, _ = workloads.graded(m, n, seeds[0], seeds[1], smin)
+else:
+    A = workloads.gaussian(m, n, seeds[0])
+t0 = time.perf_counter()
+if variant == "rbidiag":
+    oracle.rbidiag_reduce(A, nb)
+else:
+    oracle.band_reduce(A, nb)
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "threads": oracle.num_threads(),
+                  "gflops": workloads.flops_bidiag(m, n) / dt / 1e9}))
+"""
+
+
+def oracle_cfg_rate(m, n, nb, variant, kind, seeds, smin=0.0, threads=None):
+    """The oracle on one m x n matrix of a workload's recipe (gaussian or
+    graded; BiDiag or R-BiDiag), in a child process so that the OpenMP thread
+    count can be set; GFLOP/s with the metric count 4n^2(m - n/3)."""
+    env = dict(os.environ)
+    if threads is not None:
+        env["OMP_NUM_THREADS"] = str(threads)
+    code = ORACLE_CFG_SNIPPET % (HERE, m, n, nb, variant, kind, seeds[0], seeds[1], smin)
+    out = subprocess.check_output([sys.executable, "-c", code], env=env)
+    r = json.loads(out.decode().strip().splitlines()[-1])
+    return {"gflops": round(r["gflops"], 3), "seconds": round(r["seconds"], 2), "cores": r["threads"]}
+
+
+def cpu_oracle_configs():
+    """The oracle on the other workloads' recipes: the 512 x 512 N(0,1) square
+    (nb = 64, BiDiag) in full at all cores and one thread, the 8192 x 1024
+    N(0,1) adjoint workload's forward (nb = 128, R-BiDiag) in full at all
+    cores, and a 4096 x 2048 sample of the tall graded recipe (nb = 128,
+    R-BiDiag) at all cores."""
+    import oracle
+    oracle.build()
+    return {
+        "small_square_512x512_nb64_bidiag": {
+            "all_cores": oracle_cfg_rate(512, 512, 64, "bidiag", "gaussian", (0, 0)),
+            "one_thread": oracle_cfg_rate(512, 512, 64, "bidiag", "gaussian", (0, 0), threads=1)},
+        "adjoint_forward_8192x1024_nb128_rbidiag": {
+            "all_cores": oracle_cfg_rate(8192, 1024, 128, "rbidiag", "gaussian", (6, 0))},
+        "tall_graded_sample_4096x2048_nb128_rbidiag": {
+            "all_cores": oracle_cfg_rate(4096, 2048, 128, "rbidiag", "graded", (1, 2), 1e-8)},
+    }
+
+
 def cpu_baseline_square():
     """The oracle on bounded samples of the square graded recipe (nb = 256):
     2048 x 2048 on all host cores, 1024 x 1024 on one thread."""
@@ -459,6 +511,8 @@ def main():
     if "batch" in wanted:
         extras["batch"] = bench_batch(args, bb, torch, np, workloads)
     cpu = None if args.no_cpu_baseline else cpu_baseline_square()
+    if not args.no_cpu_baseline:
+        extras["cpu_oracle_other_workloads"] = cpu_oracle_configs()
 
     out = {
         "metric": METRIC, "value": round(head["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
