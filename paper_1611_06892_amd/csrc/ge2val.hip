@@ -176,8 +176,8 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 // Step t of sweep k for nb > LDS_NB, on the band array in global memory, by
 // member g of the group of a.group workgroups that runs the sweep (with
 // a group of one, as bb_bnd2bd_group allows, no group barriers).  Only
-// about n / (2.5 nb) sweeps can run at once (26 at n = 16384, nb = 256), so each
-// sweep's steps are spread over a group to use the other CUs.
+// about n / (2.5 nb) sweeps can run at once (26 at n = 16384, nb = 256), so
+// each sweep's steps are spread over a group to use the other CUs.
 //   * Every member reads row rr and forms the right reflector (the same
 //     arithmetic, the same result); the right update M -= tau (M v) v^T of
 //     rows rr+1 .. c+L-1 of columns c .. c+L-1 is split by rows, TPR lanes a
@@ -191,13 +191,14 @@ __device__ bool wait_geq(const ChaseArgs& a, const int32_t* p, int target, int* 
 //     formed through LDS, each entry read and written once.
 //   * Group barrier: the step's updates are done.  Member 0 then writes the
 //     cleared row rr and column c (beta, zeros), which no member reads later
-//     in the step or in the next one, and publishes the step.
+//     in the step or in the next one (the corner of row rr went out with the
+//     half step, after the first group barrier).
 // In the band array entry (i, j+1) follows entry (i, j) at a distance of
 // ldw - 1.  false: an error was reported or the watchdog fired.
 constexpr int GROUP_NB = 64;
 constexpr int GROUP_MAX = 16;
 constexpr int CHUNK = 32;
-constexpr int PLD = NT + 8;
+constexpr int PLD = NT + 8;              // LDS stride of a product column: lanes 8u+s hit distinct banks
 constexpr int RB = 32;                   // loads in flight per thread in the row passes
 constexpr int TPR = 4;                   // lanes a row in the right update
 
@@ -205,7 +206,7 @@ constexpr int TPR = 4;                   // lanes a row in the right update
 // not for its global loads, so loads issued before it stay in flight.
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}              // LDS stride of a product column: lanes 8u+s hit distinct banks
+}
 
 // The half of step t of sweep k that the next sweep waits for: the corner
 // (rr, c), the first entry of the row the right reflector clears, is final
@@ -213,9 +214,8 @@ __device__ __forceinline__ void lds_barrier() {
 // LDS steps hold a newer value than memory even then), waits for the store
 // and moves the progress counter to 2t+1; every earlier store of the sweep
 // has completed too, each wave having waited for its own before the
-// preceding barrier (2T marks the whole sweep).  The
-// step's own stores leave the corner alone afterwards: the next sweep
-// changes it from here on.
+// preceding barrier (2T marks the whole sweep).  The step's own stores leave
+// the corner alone afterwards: the next sweep changes it from here on.
 __device__ __forceinline__ void publish_corner(const ChaseArgs& a, int64_t k, int64_t t, double* corner,
                                                double beta) {
     if (threadIdx.x < 64) {
