@@ -472,6 +472,27 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
  */
 int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* stream);
 
+/*
+ * bb_ge2val -- singular values of the m x n matrix A by the whole GE2VAL
+ * pipeline of Sections 2 and 6.2 in stream order: bidiag_band (GE2BND, plan
+ * cached as there; A is overwritten by its band form B and vt holds the
+ * reflectors), bb_bnd2bd on B (for m < n on the transpose of the lower
+ * band) and bb_bd2val into sigma[0..min(m,n)-1] (device), in decreasing
+ * order.  ws: one workspace of bb_ge2val_workspace bytes, used by each step
+ * in turn; the band reduction's status word is kept through the chase, so
+ * bb_poll_error(ws) after the call reports the first error of the pipeline
+ * (a failed reduction stops the chase at its first wait; sigma is then
+ * undefined).  opts->watchdog_s bounds the chase's waits too.  Arguments as
+ * bidiag_band: A (1), m (2), n (3), lda (4), nb (5, at most 256), tree (6),
+ * variant (7), prec (8); sigma (9); vt (10), vt_bytes (11), ws (12),
+ * ws_bytes (13), opts (14), stream (15).  -9: sigma NULL; BB_EWORKSPACE:
+ * vt or ws too small; bidiag_band's codes otherwise.
+ */
+int bb_ge2val_workspace(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
+                        size_t* vt_bytes, size_t* ws_bytes);
+int bb_ge2val(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, int variant, int prec, double* sigma,
+              void* vt, size_t vt_bytes, void* ws, size_t ws_bytes, const bb_opts* opts, void* stream);
+
 /* Drop every plan the one-shot entry points cache (bidiag_band, bb_query,
  * bidiag_band_batched).  Plans in use by a running call are released when
  * that call returns. */

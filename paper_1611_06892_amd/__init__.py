@@ -60,7 +60,8 @@ EXPORTS = ["bb_plan_create", "bb_plan_destroy", "bb_plan_workspace", "bb_plan_ge
            "bb_batch_info", "bb_batch_execute", "bb_batch_last_kernel_ms", "bb_batch_poll_error",
            "bb_query_batched", "bidiag_band_batched", "bidiag_band_adjoint",
            "bb_adjoint_workspace", "bb_adjoint_poll_error", "bb_plan_trace", "bb_cache_clear",
-           "bb_execute_noalloc", "bb_choose", "bb_bnd2bd_workspace", "bb_bnd2bd", "bb_bnd2bd_group", "bb_bd2val"]
+           "bb_execute_noalloc", "bb_choose", "bb_bnd2bd_workspace", "bb_bnd2bd", "bb_bnd2bd_group", "bb_bd2val",
+           "bb_ge2val_workspace", "bb_ge2val"]
 
 
 def lib():
@@ -153,6 +154,12 @@ def lib():
     L.bb_bnd2bd_group.restype = i32
     L.bb_bd2val.argtypes = [vp, vp, i64, vp, vp]
     L.bb_bd2val.restype = i32
+    L.bb_ge2val_workspace.argtypes = [i64, i64, i32, i32, i32, i32, ctypes.POINTER(_Opts),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    L.bb_ge2val_workspace.restype = i32
+    L.bb_ge2val.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
+                            ctypes.POINTER(_Opts), vp]
+    L.bb_ge2val.restype = i32
     L.bb_cache_clear.argtypes = []
     L.bb_cache_clear.restype = None
     L.bb_plan_trace.argtypes = [P, szp, lp, ctypes.POINTER(ctypes.c_double), vp]
@@ -481,6 +488,32 @@ def ge2val(A, nb, tree="auto", variant="bidiag", **opts):
     S = B.t()                      # the column-major storage, leading dimension m
     d, e = bnd2bd(S, m, n, nb)
     return bd2val(d, e)
+
+
+def ge2val_oneshot(A, nb, tree="auto", variant="bidiag", prec="f64", stream=None, check=True, **opts):
+    """Singular values of A through the C one-shot bb_ge2val (GE2BND, BND2BD
+    and BD2VAL in stream order, one workspace), in decreasing order, as a
+    CUDA tensor.  A is not modified (the reduction runs on a copy)."""
+    import torch
+    m, n = A.shape
+    S = to_colmajor(A)
+    o = make_opts(**opts)
+    vtb, wsb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().bb_ge2val_workspace(int(m), int(n), int(nb), TREES[tree], VARIANTS[variant], PRECS[prec],
+                                     ctypes.byref(o), ctypes.byref(vtb), ctypes.byref(wsb)), "bb_ge2val_workspace")
+    vt = torch.empty(max(vtb.value, 8), dtype=torch.uint8, device=S.device)
+    ws = torch.empty(max(wsb.value, 8), dtype=torch.uint8, device=S.device)
+    k = min(m, n)
+    sigma = torch.empty(max(k, 1), dtype=torch.float64, device=S.device)
+    _check(lib().bb_ge2val(ctypes.c_void_p(S.data_ptr()), int(m), int(n), int(m), int(nb), TREES[tree],
+                           VARIANTS[variant], PRECS[prec], ctypes.c_void_p(sigma.data_ptr()),
+                           ctypes.c_void_p(vt.data_ptr()), vt.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                           ctypes.byref(o), _stream_handle(stream)), "bb_ge2val")
+    if check:
+        st = poll_error(ws, stream)
+        if st != 0:
+            raise BidiagError(st, "ge2val pipeline")
+    return sigma[:k]
 
 
 TREE_NAMES = {v: k for k, v in TREES.items()}

@@ -572,12 +572,16 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
 }
 
 // Copy the upper band of B into W (zero elsewhere), clear the control words
-// and the progress counters.
-__global__ void pack_kernel(const double* B, int64_t ldb, int64_t n, int nb, double* W, int64_t ldw,
-                            int32_t* ctrl, int32_t* prog, int32_t* bar, int nsweeps) {
+// (the error word too unless keep_error: then a status already there, such as
+// the band reduction's in the one-shot pipeline, stops the chase at its
+// first wait and stays visible) and the progress counters.  Entry (i, j) of
+// the band is B[i rs + j cs]: rs = 1, cs = ldb for an upper band stored as
+// is, rs = ldb, cs = 1 for the transpose of a lower band.
+__global__ void pack_kernel(const double* B, int64_t rs, int64_t cs, int64_t n, int nb, double* W, int64_t ldw,
+                            int32_t* ctrl, int32_t* prog, int32_t* bar, int nsweeps, int keep_error) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (g < G_WORDS) ctrl[g] = 0;
+    if (g < G_WORDS && !(keep_error && g == G_ERROR)) ctrl[g] = 0;
     for (int64_t s = g; s < nsweeps; s += stride) {
         prog[s] = 0;
         bar[s] = 0;
@@ -586,7 +590,7 @@ __global__ void pack_kernel(const double* B, int64_t ldb, int64_t n, int nb, dou
     for (int64_t x = g; x < total; x += stride) {
         const int64_t j = x / ldw;
         const int64_t i = j + (x - j * ldw) - (2 * nb - 1);
-        W[x] = (i >= 0 && i <= j && j - i <= nb) ? B[i + j * ldb] : 0.0;
+        W[x] = (i >= 0 && i <= j && j - i <= nb) ? B[i * rs + j * cs] : 0.0;
     }
 }
 
@@ -695,6 +699,18 @@ int bb_bnd2bd_workspace(int64_t n, int nb, size_t* ws_bytes) {
     return BB_OK;
 }
 
+}  // extern "C"
+
+namespace bbg {
+
+// The chase after argument checks: band entry (i, j) at B[i rs + j cs].
+int bnd2bd_launch(const double* B, int64_t rs, int64_t cs, int64_t n, int nb, double* d, double* e, void* ws,
+                  double watchdog_s, int group, bool keep_error, void* stream);
+
+}  // namespace bbg
+
+extern "C" {
+
 int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
                     size_t ws_bytes, double watchdog_s, int group, void* stream) {
     if (group < 0 || group > bbg::GROUP_MAX) return -10;
@@ -707,6 +723,13 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
     if (!ws && n > 0) return -7;
     if (ws_bytes < bbg::ws_bytes(n, nb)) return BB_EWORKSPACE;
     if (n == 0) return BB_OK;
+    return bbg::bnd2bd_launch(B, 1, ldb, n, nb, d, e, ws, watchdog_s, group, false, stream);
+}
+
+}  // extern "C"
+
+int bbg::bnd2bd_launch(const double* B, int64_t rs, int64_t cs, int64_t n, int nb, double* d, double* e,
+                       void* ws, double watchdog_s, int group, bool keep_error, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int nsw = bbg::nsweeps_of(n, nb);
     bbg::ChaseArgs a;
@@ -723,8 +746,8 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
     const int cus = bbg::device_attr(hipDeviceAttributeMultiprocessorCount, 256);
     const int64_t total = a.ldw * n;
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 8 * (int64_t)cus);
-    hipLaunchKernelGGL(bbg::pack_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, B, ldb, n, nb, a.W,
-                       a.ldw, a.ctrl, a.prog, a.bar, nsw);
+    hipLaunchKernelGGL(bbg::pack_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, B, rs, cs, n, nb, a.W,
+                       a.ldw, a.ctrl, a.prog, a.bar, nsw, keep_error ? 1 : 0);
     if (hipGetLastError() != hipSuccess) return BB_EHIP;
     // nb > GROUP_NB: a group of ceil(nb / 16) workgroups a sweep, so that a
     // member takes about 32 rows of the right update and one 32-column chunk
@@ -751,6 +774,8 @@ int bb_bnd2bd_group(const double* B, int64_t ldb, int64_t n, int nb, double* d, 
     return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
 }
 
+extern "C" {
+
 int bb_bnd2bd(const double* B, int64_t ldb, int64_t n, int nb, double* d, double* e, void* ws,
               size_t ws_bytes, double watchdog_s, void* stream) {
     return bb_bnd2bd_group(B, ldb, n, nb, d, e, ws, ws_bytes, watchdog_s, 0, stream);
@@ -773,6 +798,50 @@ int bb_bd2val(const double* d, const double* e, int64_t n, double* sigma, void* 
         default: hipLaunchKernelGGL(bbg::bisect_kernel<32>, grid, dim3(256), 0, s, d, e, n, sigma); break;
     }
     return hipGetLastError() == hipSuccess ? BB_OK : BB_EHIP;
+}
+
+// bb_ge2val's workspace: the band reduction's, and after it (stream order)
+// the chase's with the bidiagonal (d, e) behind it.
+static int ge2val_sizes(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
+                        size_t* vt_bytes, size_t* ws_bytes, size_t* de_off) {
+    size_t vt = 0, wsb = 0;
+    const int rc = bb_query(m, n, nb, tree, variant, prec, opts, &vt, &wsb);
+    if (rc != BB_OK) return rc;
+    const int64_t k = m < n ? m : n;
+    const size_t chase = bbg::ws_bytes(k, nb);
+    const size_t off = (chase + 255) / 256 * 256;
+    const size_t need = off + (size_t)(2 * (k > 0 ? k : 1)) * sizeof(double);
+    if (vt_bytes) *vt_bytes = vt;
+    if (ws_bytes) *ws_bytes = wsb > need ? wsb : need;
+    if (de_off) *de_off = off;
+    return BB_OK;
+}
+
+int bb_ge2val_workspace(int64_t m, int64_t n, int nb, int tree, int variant, int prec, const bb_opts* opts,
+                        size_t* vt_bytes, size_t* ws_bytes) {
+    if (!vt_bytes || !ws_bytes) return -8;
+    return ge2val_sizes(m, n, nb, tree, variant, prec, opts, vt_bytes, ws_bytes, nullptr);
+}
+
+int bb_ge2val(void* A, int64_t m, int64_t n, int64_t lda, int nb, int tree, int variant, int prec, double* sigma,
+              void* vt, size_t vt_bytes, void* ws, size_t ws_bytes, const bb_opts* opts, void* stream) {
+    size_t need_vt = 0, need_ws = 0, de_off = 0;
+    int rc = ge2val_sizes(m, n, nb, tree, variant, prec, opts, &need_vt, &need_ws, &de_off);
+    if (rc != BB_OK) return rc;
+    const int64_t k = m < n ? m : n;
+    if (!sigma && k > 0) return -9;
+    if (vt_bytes < need_vt || ws_bytes < need_ws) return BB_EWORKSPACE;
+    rc = bidiag_band(A, m, n, lda, nb, tree, variant, prec, vt, vt_bytes, ws, ws_bytes, opts, stream);
+    if (rc != BB_OK || k == 0) return rc;
+    double* d = (double*)((char*)ws + de_off);
+    double* e = d + k;
+    // m >= n: upper band in the leading n x n part; m < n: lower band in the
+    // leading m x m part, chased as its transpose
+    const double* B = (const double*)A;
+    rc = m >= n ? bbg::bnd2bd_launch(B, 1, lda, k, nb, d, e, ws, opts ? opts->watchdog_s : 0.0, 0, true, stream)
+                : bbg::bnd2bd_launch(B, lda, 1, k, nb, d, e, ws, opts ? opts->watchdog_s : 0.0, 0, true, stream);
+    if (rc != BB_OK) return rc;
+    return bb_bd2val(d, e, k, sigma, stream);
 }
 
 }  // extern "C"

@@ -241,3 +241,34 @@ def test_bnd2bd_watchdog_reports_timeout_and_recovers(bb, n, nb):
     tol = 50 * n * EPS * np.linalg.norm(og.upper_band(A, n, nb))
     assert np.max(np.abs(np.abs(d.cpu().numpy()) - np.abs(do))) <= tol
     assert np.max(np.abs(np.abs(e.cpu().numpy()) - np.abs(eo))) <= tol
+
+
+@pytest.mark.parametrize("m,n,nb,tree,variant", [(1024, 512, 64, "auto", "bidiag"), (600, 900, 128, "greedy", "bidiag"),
+                                                 (700, 700, 256, "auto", "bidiag"), (2000, 300, 32, "greedy", "rbidiag"),
+                                                 (333, 500, 64, "greedy", "bidiag")])
+def test_ge2val_oneshot_returns_prescribed_singular_values(bb, m, n, nb, tree, variant):
+    """bb_ge2val (the C one-shot: GE2BND, BND2BD on the band or on the
+    transpose of the lower band of a wide matrix, BD2VAL, one workspace)
+    on graded inputs: the prescribed singular values."""
+    print("case ge2val one-shot", m, n, nb, tree, variant, flush=True)
+    A, s = workloads.graded(max(m, n), min(m, n), 51, 52, 1e-6)
+    if m < n:
+        A = np.ascontiguousarray(A.T)
+    sg = bb.ge2val_oneshot(torch.from_numpy(A), nb, tree, variant, watchdog_s=20.0).cpu().numpy()
+    ref = np.sort(s)[::-1]
+    assert np.max(np.abs(sg - ref)) <= 50 * max(m, n) * EPS * ref[0]
+
+
+def test_ge2val_oneshot_reports_a_failed_reduction(bb):
+    """A band-reduction watchdog of no clock ticks, set from the host: the
+    reduction reports BB_ETIMEOUT, the chase keeps that status and stops at
+    its first wait, every launch ends normally, and bb_poll_error reports it;
+    the next call gives the prescribed singular values."""
+    m, n, nb = 1500, 1000, 64
+    A, s = workloads.graded(m, n, 53, 54, 1e-6)
+    with pytest.raises(bb.BidiagError) as err:
+        bb.ge2val_oneshot(torch.from_numpy(A), nb, "greedy", "bidiag", watchdog_s=1e-12)
+    assert err.value.code == 3          # BB_ETIMEOUT
+    sg = bb.ge2val_oneshot(torch.from_numpy(A), nb, "greedy", "bidiag", watchdog_s=20.0).cpu().numpy()
+    ref = np.sort(s)[::-1]
+    assert np.max(np.abs(sg - ref)) <= 50 * m * EPS * ref[0]
