@@ -11,7 +11,14 @@ bidiagonal), and the whole GE2BND + BND2BD + BD2VAL pipeline.
 * the device bisection matches the oracle's singular values within
   50 n eps ||B||_2 (an absolute bound: bisection is accurate to a few
   eps ||B||);
-* the pipeline returns the prescribed singular values of graded inputs.
+* the pipeline returns the prescribed singular values of graded inputs, up to
+  the full 16384 x 16384 square in the bench's launch configuration, both
+  chained from the Python binding and as the C one-shot bb_ge2val;
+* the chase's result does not depend on how many workgroups run a sweep
+  (bit-identical for groups of 1 to 16);
+* failure handling forced from the host: a watchdog of no clock ticks makes
+  the launch end normally with BB_ETIMEOUT, through the one-shot pipeline too,
+  and the next call is correct.
 """
 import numpy as np
 import pytest
