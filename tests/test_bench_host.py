@@ -6,6 +6,8 @@
 * measured_traffic reports the committed HBM traffic only while the kernel
   source hashes to the value recorded beside it.
 * --gpus above 1 exits with a message, since the path is single-GPU.
+* chase_bytes (the bulge chase's algorithmic bytes) equals 16 bytes per entry
+  that a brute-force count finds changed in each step.
 """
 import hashlib
 import os
@@ -99,3 +101,33 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _chase_changed_entries(n, nb):
+    """Entries each step of the bulge chase changes, counted as sets from the
+    step's definition: the right reflector of step t of sweep k (column
+    c = k + 1 + t nb) acts on columns c .. c+L-1 of rows rr .. c+L-1 (the
+    cleared row rr = k, or c - nb after the first step, and every row below
+    it down to the diagonal block); the left one on rows c .. c+L-1 of
+    columns c .. min(c + 2 nb, n) - 1.  L = min(nb, n - c)."""
+    total = 0
+    if nb <= 1:
+        return 0
+    for k in range(max(n - 2, 0)):
+        c, t = k + 1, 0
+        while c < n:
+            L = min(nb, n - c)
+            rr = k if t == 0 else c - nb
+            cells = {(i, j) for i in range(rr, c + L) for j in range(c, c + L)}
+            cells |= {(i, j) for i in range(c, c + L) for j in range(c, min(c + 2 * nb, n))}
+            total += len(cells)
+            c += nb
+            t += 1
+    return total
+
+
+@pytest.mark.parametrize("n,nb", [(1, 4), (2, 1), (5, 2), (9, 3), (17, 4), (40, 7), (33, 16), (12, 20)])
+def test_chase_bytes_counts_every_changed_entry_once_per_step(n, nb):
+    """The chase's algorithmic bytes (16 per changed entry and step, read and
+    written once) against a brute-force count of the changed entries."""
+    assert bench.chase_bytes(n, nb) == 16 * _chase_changed_entries(n, nb)
